@@ -1,0 +1,263 @@
+"""Python face of the CPU oracle (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may import
+this module.  It loads ``liboracle.so`` (plain C, built from ``boys_oracle.c`` by
+``build()`` below) and reads the coefficient dataset with its own parser.  It shares
+no code with the GPU library or its Python binding.
+
+Functions
+---------
+exact(x, mmax)            F_m(x), m = 0..mmax, from the definition (Eq. fn), as
+                          double-double (hi, lo) arrays of shape (mmax+1, len(x)).
+approx_f64(x, n)          the binary64 approximant (Eqs. fq, pqz, pz, qz, r, limf1),
+                          shape (n+1, len(x)), float64.
+approx_mixed(x, n)        the mixed binary32/binary64 class, shape (n+1, len(x)), float32.
+approx_exact_n(x, n)      F~_n in binary128 from the 40-digit coefficients, as (hi, lo).
+exp_neg(x)                correctly rounded exp(-x) as both approximants use it.
+load_dataset(path)        the parsed coefficient dataset.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+REPO = os.path.dirname(HERE)
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC = os.path.join(HERE, "boys_oracle.c")
+DATASET = os.path.join(REPO, "paper_2504_07637_amd", "data", "boys_coeffs.txt")
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain IEEE arithmetic, no contraction)."""
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", "-o", LIB_PATH + ".tmp", SRC, "-lquadmath", "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        fp = ctypes.POINTER(ctypes.c_float)
+        i64 = ctypes.c_int64
+        L.oracle_boys_exact.argtypes = [dp, i64, ctypes.c_int, dp, dp]
+        L.oracle_boys_approx_f64.argtypes = [dp, i64, dp, ctypes.c_int, dp, i64]
+        L.oracle_boys_approx_mixed.argtypes = [dp, i64, dp, ctypes.c_int, fp, i64]
+        L.oracle_boys_approx_q.argtypes = [dp, i64, dp, dp, dp]
+        L.oracle_exp_neg.argtypes = [dp, i64, dp]
+        for f in (L.oracle_boys_exact, L.oracle_boys_approx_f64, L.oracle_boys_approx_mixed,
+                  L.oracle_boys_approx_q, L.oracle_exp_neg):
+            f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _fp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+# ------------------------------------------------------------------------------------
+# dataset
+
+
+class Record:
+    """One (precision class, n) approximant.  Fields hold Python floats (hex-exact)
+    and, with suffix ``x``, Fractions of the 40-digit decimal values."""
+
+    def __init__(self, cls, n, N):
+        self.cls, self.n, self.N = cls, n, N
+        self.fields = {}
+
+    def __getitem__(self, k):
+        return self.fields[k]
+
+
+def _parse_hex_list(tok, pairs=False):
+    k = int(tok[0])
+    vals = [float.fromhex(t) for t in tok[1:]]
+    if len(vals) != (2 * k if pairs else k):
+        raise ValueError("bad count in dataset line")
+    return vals
+
+
+def _parse_dec_list(tok, pairs=False):
+    k = int(tok[0])
+    vals = [Fraction(t) for t in tok[1:]]
+    if len(vals) != (2 * k if pairs else k):
+        raise ValueError("bad count in dataset line")
+    return vals
+
+
+def load_dataset(path: str = DATASET):
+    recs = {}
+    c0 = None
+    cur = None
+    with open(path) as fh:
+        for raw in fh:
+            line = raw.split("#", 1)[0].strip()
+            if not line:
+                continue
+            tok = line.split()
+            key = tok[0]
+            if key == "format":
+                if tok[1:] != ["boys-coeffs", "1"]:
+                    raise ValueError("unknown dataset format")
+            elif key == "c0":
+                c0 = float.fromhex(tok[1])
+            elif key == "record":
+                cur = Record(tok[1], int(tok[2]), int(tok[3]))
+            elif key == "end":
+                cur.fields["c0"] = c0
+                recs[(cur.cls, cur.n)] = cur
+                cur = None
+            elif key in ("c", "z", "q0", "q1", "q2"):
+                cur.fields[key] = float.fromhex(tok[1])
+                cur.fields[key + "x"] = Fraction(tok[2])
+            elif key in ("ug", "ul", "vg", "vl"):
+                cur.fields[key] = _parse_hex_list(tok[1:])
+            elif key in ("uq", "vq"):
+                cur.fields[key] = _parse_hex_list(tok[1:], pairs=True)
+            elif key in ("ugx", "ulx", "vgx", "vlx"):
+                cur.fields[key] = _parse_dec_list(tok[1:])
+            elif key in ("uqx", "vqx"):
+                cur.fields[key] = _parse_dec_list(tok[1:], pairs=True)
+            elif key in ("A", "B"):
+                cur.fields[key] = _parse_dec_list(tok[1:])
+            elif key == "eps":
+                cur.fields["eps"] = (float(tok[1]), float(tok[2]))
+            else:
+                raise ValueError(f"unknown dataset key {key!r}")
+    return recs
+
+
+_DATA = None
+
+
+def dataset():
+    global _DATA
+    if _DATA is None:
+        _DATA = load_dataset()
+    return _DATA
+
+
+def record(cls: str, n: int) -> Record:
+    return dataset()[(cls, n)]
+
+
+def flat_record(r: Record) -> np.ndarray:
+    """The rec[] layout of boys_oracle.c."""
+    f = r.fields
+    out = [float(r.n), f["c"], f["z"], f["q0"], f["q1"], f["q2"], f["c0"]]
+    for side in ("u", "v"):
+        g, q, l = f[side + "g"], f[side + "q"], f[side + "l"]
+        out += [float(len(g))] + g + [float(len(q) // 2)] + q + [float(len(l))] + l
+    return np.array(out, dtype=np.float64)
+
+
+def _dd(fr: Fraction):
+    hi = float(fr)
+    lo = float(fr - Fraction(hi))
+    return [hi, lo]
+
+
+def flat_record_ext(r: Record, fields=None) -> np.ndarray:
+    """The recx[] layout of boys_oracle.c (double-double coefficients)."""
+    f = dict(r.fields)
+    if fields:
+        f.update(fields)
+    out = [float(r.n)]
+    for k in ("q0x", "q1x", "q2x"):
+        out += _dd(f[k])
+    for side in ("u", "v"):
+        g, q, l = f[side + "gx"], f[side + "qx"], f[side + "lx"]
+        out += [float(len(g))]
+        for v in g:
+            out += _dd(v)
+        out += [float(len(q) // 2)]
+        for v in q:
+            out += _dd(v)
+        out += [float(len(l))]
+        for v in l:
+            out += _dd(v)
+    return np.array(out, dtype=np.float64)
+
+
+# ------------------------------------------------------------------------------------
+# evaluators
+
+
+def exact(x, mmax: int):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    hi = np.empty((mmax + 1, x.size))
+    lo = np.empty((mmax + 1, x.size))
+    rc = lib().oracle_boys_exact(_dp(x), x.size, mmax, _dp(hi), _dp(lo))
+    if rc:
+        raise ValueError("oracle_boys_exact rejected its arguments")
+    return hi, lo
+
+
+def approx_f64(x, n: int, rec: Record | None = None):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    r = rec if rec is not None else record("fp64", n)
+    fr = flat_record(r)
+    out = np.empty((n + 1, x.size))
+    rc = lib().oracle_boys_approx_f64(_dp(x), x.size, _dp(fr), fr.size, _dp(out), x.size)
+    if rc:
+        raise ValueError("oracle_boys_approx_f64 rejected its arguments")
+    return out
+
+
+def approx_mixed(x, n: int, rec: Record | None = None):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    r = rec if rec is not None else record("fp32", n)
+    fr = flat_record(r)
+    out = np.empty((n + 1, x.size), dtype=np.float32)
+    rc = lib().oracle_boys_approx_mixed(_dp(x), x.size, _dp(fr), fr.size, _fp(out), x.size)
+    if rc:
+        raise ValueError("oracle_boys_approx_mixed rejected its arguments")
+    return out
+
+
+def approx_exact_n(x, n: int, cls: str = "fp64", fields=None):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    fr = flat_record_ext(record(cls, n), fields)
+    hi = np.empty(x.size)
+    lo = np.empty(x.size)
+    lib().oracle_boys_approx_q(_dp(x), x.size, _dp(fr), _dp(hi), _dp(lo))
+    return hi, lo
+
+
+def exp_neg(x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty(x.size)
+    lib().oracle_exp_neg(_dp(x), x.size, _dp(out))
+    return out
+
+
+def rel_err(approx, hi, lo):
+    """(approx - F) / F with F = hi + lo, elementwise, in binary64."""
+    a = np.asarray(approx, dtype=np.float64)
+    return ((a - hi) - lo) / hi
+
+
+def bits(e) -> float:
+    """-log2 of the largest |e|."""
+    m = float(np.max(np.abs(e)))
+    return float("inf") if m == 0 else -np.log2(m)

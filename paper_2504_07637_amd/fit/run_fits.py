@@ -1,0 +1,176 @@
+"""Fit every (precision class, n) approximant and write the coefficient dataset.
+
+Usage:  python -m paper_2504_07637_amd.fit.run_fits [--nmax 36] [--jobs 7] [--out PATH]
+
+The orders N follow Table 1 of the paper (blank cells read as repeats of the cell
+above): binary64 N = 10 (n = 0-1), 11 (2-6), 12 (7-10), 13 (11-17), 14 (18-36);
+binary32 N = 4 (0-1), 5 (2-9), 6 (10-36).  The cut-off z_nb uses b = 53 for the
+binary64 class and b = 24 for the binary32 class.
+
+Dataset format (text, one token list per line, '#' starts a comment):
+
+    format boys-coeffs 1
+    c0 <hex>                         c_0 = sqrt(pi)/2 in binary64
+    record <fp64|fp32> <n> <N>
+    c  <hex> <dec>                   c_n (binary64)
+    z  <hex> <dec>                   z_nb (binary64)
+    q0 <hex> <dec>                   Q_n(0)        } working precision of the class
+    q1 <hex> <dec>                   Q'_n(0)       } (binary32 values for fp32)
+    q2 <hex> <dec>                   alpha_n - q1  }
+    ug <k> <hex>*k                   gathered monic factor of u, ascending, leading 1 implied
+    uq <k> (<hex y> <hex a>)*k       factors (x - y)^2 + a of u, ascending y
+    ul <k> <hex>*k                   factors (x - y) of u
+    vg / vq / vl                     the same for v
+    ugx / uqx / ulx / vgx / vqx / vlx   the same values with 40 significant decimal digits
+    A <N+2> <dec>*                   expanded numerator of Eq. qr
+    B <N+1> <dec>*                   expanded denominator of Eq. qr (B_0 = 1)
+    eps <exact coefficients> <rounded coefficients>   -log2 max|F~/F-1| on [0, z_nb)
+    end
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mproc
+import os
+import sys
+import time
+
+import mpmath as mp
+
+from . import boys_fit as bf
+
+DATA_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "data")
+DEFAULT_OUT = os.path.join(DATA_DIR, "boys_coeffs.txt")
+REPORT = os.path.join(DATA_DIR, "fit_report.json")
+
+
+def table1_N(cls: str, n: int) -> int:
+    if cls == "fp64":
+        return 10 if n <= 1 else 11 if n <= 6 else 12 if n <= 10 else 13 if n <= 17 else 14
+    return 4 if n <= 1 else 5 if n <= 9 else 6
+
+
+def _fit_one(job):
+    cls, n = job
+    mp.mp.prec = bf.PREC
+    b = 53 if cls == "fp64" else 24
+    N = table1_N(cls, n)
+    t0 = time.time()
+    attempts = [(500 if cls == "fp64" else 300, 1.0), (800, 1.0), (800, 1.1)]
+    last_err = None
+    for M, xs in attempts:
+        try:
+            r = bf.fit(n, N, b, M=M, iters=600 if cls == "fp64" else 300, X_scale=xs)
+            cn = bf.consts(n)
+            f = bf.factor(cn, r.A, r.B)
+            # no pole on [0, inf): every linear factor of v must have a negative root
+            if f.vl:
+                raise RuntimeError(f"v has real non-negative roots {f.vl}")
+            if r.B[-1] <= 0:
+                raise RuntimeError("B_N <= 0 (rejected, as in the paper)")
+            for y, a in f.uq + f.vq:
+                if a <= 0:
+                    raise RuntimeError("non-positive a in a quadratic factor")
+            fr = bf.round_factored(f, cls == "fp32")
+            eps_x = bf.dense_error(n, f, r.z, npts=1500)
+            eps_r = bf.dense_error(n, fr, r.z, npts=1500)
+            break
+        except Exception as exc:  # try the next sampling
+            last_err = exc
+            r = None
+    if r is None:
+        return {"cls": cls, "n": n, "N": N, "error": repr(last_err)}
+    to_hex = bf.to_f32_hex if cls == "fp32" else (lambda v: bf.hexf(float(v)))
+    rec = {
+        "cls": cls, "n": n, "N": N, "b": b,
+        "c": (bf.hexf(float(cn.c)), bf.decs(cn.c)),
+        "z": (bf.hexf(float(r.z)), bf.decs(r.z)),
+        "q0": (to_hex(f.q0), bf.decs(f.q0)),
+        "q1": (to_hex(f.q1), bf.decs(f.q1)),
+        "q2": (to_hex(f.q2), bf.decs(f.q2)),
+        "ug": [to_hex(c) for c in f.ug], "ugx": [bf.decs(c) for c in f.ug],
+        "uq": [(to_hex(y), to_hex(a)) for y, a in f.uq],
+        "uqx": [(bf.decs(y), bf.decs(a)) for y, a in f.uq],
+        "ul": [to_hex(y) for y in f.ul], "ulx": [bf.decs(y) for y in f.ul],
+        "vg": [to_hex(c) for c in f.vg], "vgx": [bf.decs(c) for c in f.vg],
+        "vq": [(to_hex(y), to_hex(a)) for y, a in f.vq],
+        "vqx": [(bf.decs(y), bf.decs(a)) for y, a in f.vq],
+        "vl": [to_hex(y) for y in f.vl], "vlx": [bf.decs(y) for y in f.vl],
+        "A": [bf.decs(a) for a in r.A], "B": [bf.decs(b_) for b_ in r.B],
+        "eps_exact": eps_x, "eps_rounded": eps_r, "eps_sampled": r.err_sampled,
+        "iterations": r.iterations, "seconds": time.time() - t0,
+    }
+    print(f"[fit] {cls} n={n} N={N} eps={eps_x:.2f} (rounded {eps_r:.2f}) "
+          f"{time.time() - t0:.0f}s", flush=True)
+    return rec
+
+
+def _line(tag, vals):
+    return tag + " " + str(len(vals)) + ("" if not vals else " " + " ".join(vals))
+
+
+def _pairs(tag, pairs):
+    return f"{tag} {len(pairs)}" + "".join(f" {a} {b}" for a, b in pairs)
+
+
+def write_dataset(records, path):
+    mp.mp.prec = bf.PREC
+    c0 = mp.sqrt(mp.pi) / 2
+    out = ["# Boys-function approximant coefficients (root-factored form of Eqs. pqz, pz, qz)",
+           "# written by paper_2504_07637_amd.fit.run_fits; see that module for the format",
+           "format boys-coeffs 1",
+           f"c0 {bf.hexf(float(c0))}"]
+    for r in sorted(records, key=lambda r: (r["cls"], r["n"])):
+        out.append(f"record {r['cls']} {r['n']} {r['N']}")
+        for k in ("c", "z", "q0", "q1", "q2"):
+            out.append(f"{k} {r[k][0]} {r[k][1]}")
+        for side in ("u", "v"):
+            out.append(_line(side + "g", r[side + "g"]))
+            out.append(_pairs(side + "q", r[side + "q"]))
+            out.append(_line(side + "l", r[side + "l"]))
+        for side in ("u", "v"):
+            out.append(_line(side + "gx", r[side + "gx"]))
+            out.append(_pairs(side + "qx", r[side + "qx"]))
+            out.append(_line(side + "lx", r[side + "lx"]))
+        out.append(_line("A", r["A"]))
+        out.append(_line("B", r["B"]))
+        out.append(f"eps {r['eps_exact']:.3f} {r['eps_rounded']:.3f}")
+        out.append("end")
+    with open(path, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--nmax", type=int, default=36)
+    ap.add_argument("--jobs", type=int, default=max(1, (os.cpu_count() or 2) - 1))
+    ap.add_argument("--classes", default="fp64,fp32")
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    ap.add_argument("--report", default=REPORT)
+    args = ap.parse_args(argv)
+    classes = args.classes.split(",")
+    # long binary64 fits first so the pool drains evenly
+    jobs = [(c, n) for c in classes for n in range(args.nmax + 1)]
+    jobs.sort(key=lambda j: (j[0] != "fp64", -bf_cost(j)))
+    with mproc.Pool(args.jobs) as pool:
+        recs = pool.map(_fit_one, jobs, chunksize=1)
+    bad = [r for r in recs if "error" in r]
+    good = [r for r in recs if "error" not in r]
+    write_dataset(good, args.out)
+    with open(args.report, "w") as fh:
+        json.dump([{k: r[k] for k in r if k in ("cls", "n", "N", "eps_exact", "eps_rounded",
+                                                "eps_sampled", "iterations", "seconds", "error")}
+                   for r in recs], fh, indent=1)
+    for r in bad:
+        print("[fit] FAILED", r, file=sys.stderr)
+    return 1 if bad else 0
+
+
+def bf_cost(job):
+    cls, n = job
+    return table1_N(cls, n)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
