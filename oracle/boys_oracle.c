@@ -118,6 +118,29 @@ int oracle_boys_exact(const double *x, int64_t n, int mmax, double *hi, double *
     return 0;
 }
 
+/* F_m(x_i) for one order m only */
+int oracle_boys_exact_one(const double *x, int64_t n, int m, double *hi, double *lo)
+{
+    if (n < 0 || m < 0)
+        return 1;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        const double xi = x[i];
+        if (!(xi >= 0)) {
+            hi[i] = NAN;
+            lo[i] = 0;
+        } else if (isinf(xi)) {
+            hi[i] = 0;
+            lo[i] = 0;
+        } else {
+            const __float128 f = boys_exact_q((__float128)xi, m);
+            hi[i] = (double)f;
+            lo[i] = (double)(f - (__float128)hi[i]);
+        }
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------------ */
 /* coefficient records, passed flat from the Python side                            */
 /*

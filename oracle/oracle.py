@@ -9,6 +9,7 @@ Functions
 ---------
 exact(x, mmax)            F_m(x), m = 0..mmax, from the definition (Eq. fn), as
                           double-double (hi, lo) arrays of shape (mmax+1, len(x)).
+exact_one(x, m)           the same for one order m, arrays of shape (len(x),).
 approx_f64(x, n)          the binary64 approximant (Eqs. fq, pqz, pz, qz, r, limf1),
                           shape (n+1, len(x)), float64.
 approx_mixed(x, n)        the mixed binary32/binary64 class, shape (n+1, len(x)), float32.
@@ -54,11 +55,12 @@ def lib():
         fp = ctypes.POINTER(ctypes.c_float)
         i64 = ctypes.c_int64
         L.oracle_boys_exact.argtypes = [dp, i64, ctypes.c_int, dp, dp]
+        L.oracle_boys_exact_one.argtypes = [dp, i64, ctypes.c_int, dp, dp]
         L.oracle_boys_approx_f64.argtypes = [dp, i64, dp, ctypes.c_int, dp, i64]
         L.oracle_boys_approx_mixed.argtypes = [dp, i64, dp, ctypes.c_int, fp, i64]
         L.oracle_boys_approx_q.argtypes = [dp, i64, dp, dp, dp]
         L.oracle_exp_neg.argtypes = [dp, i64, dp]
-        for f in (L.oracle_boys_exact, L.oracle_boys_approx_f64, L.oracle_boys_approx_mixed,
+        for f in (L.oracle_boys_exact, L.oracle_boys_exact_one, L.oracle_boys_approx_f64, L.oracle_boys_approx_mixed,
                   L.oracle_boys_approx_q, L.oracle_exp_neg):
             f.restype = ctypes.c_int
         _lib = L
@@ -210,6 +212,17 @@ def exact(x, mmax: int):
     rc = lib().oracle_boys_exact(_dp(x), x.size, mmax, _dp(hi), _dp(lo))
     if rc:
         raise ValueError("oracle_boys_exact rejected its arguments")
+    return hi, lo
+
+
+def exact_one(x, m: int):
+    """F_m(x) for one order m, as (hi, lo)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    hi = np.empty(x.size)
+    lo = np.empty(x.size)
+    rc = lib().oracle_boys_exact_one(_dp(x), x.size, m, _dp(hi), _dp(lo))
+    if rc:
+        raise ValueError("oracle_boys_exact_one rejected its arguments")
     return hi, lo
 
 

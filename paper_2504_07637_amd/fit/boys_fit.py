@@ -223,7 +223,9 @@ def rel_err_F(cn: Consts, x, Qt, W):
 
 
 def fit(n: int, N: int, b: int, M: int = 500, iters: int = 400, verbose: bool = False,
-        X_scale: float = 1.0) -> FitResult:
+        X_scale: float = 1.0, init_B=None) -> FitResult:
+    """Lawson-SK fit; init_B (expanded denominator B_0..B_N of another fit, e.g. of a
+    neighbouring n) seeds the first linearisation instead of D = 1."""
     mp.mp.prec = PREC
     cn = consts(n)
     z = cutoff(n, b)
@@ -257,7 +259,12 @@ def fit(n: int, N: int, b: int, M: int = 500, iters: int = 400, verbose: bool = 
         bd = [mp.fdot(DLt[j], row[: N + 1]) for j in range(K)]
         base_P.append((bp, mp.fdot(par.Pa, row[: N + 2])))
         base_D.append((bd, mp.fdot(par.Db, row[: N + 1])))
-    Dprev = [_mpf(1)] * Mn
+    if init_B is not None:
+        Dprev = [_horner([mp.mpf(bk) for bk in init_B], x) for x in xs]
+        if any(d <= 0 for d in Dprev):
+            Dprev = [_mpf(1)] * Mn
+    else:
+        Dprev = [_mpf(1)] * Mn
     lam = [_mpf(1) / Mn] * Mn
     best = None
     hist = []
@@ -327,6 +334,174 @@ def fit(n: int, N: int, b: int, M: int = 500, iters: int = 400, verbose: bool = 
         raise RuntimeError(f"no admissible fit for n={n} N={N} b={b}")
     A_, B_ = par.unscaled(best[1])
     return FitResult(n, N, b, z, X, A_, B_, float(-mp.log(best[0], 2)), len(hist), hist)
+
+
+def _alternation(err, nref):
+    """Indices of nref alternating extrema of err (one per sign run, extras pruned)."""
+    runs = []
+    i = 0
+    M = len(err)
+    while i < M:
+        if err[i] == 0:
+            i += 1
+            continue
+        sgn = err[i] > 0
+        best = i
+        j = i
+        while j < M and (err[j] > 0) == sgn and err[j] != 0:
+            if abs(err[j]) > abs(err[best]):
+                best = j
+            j += 1
+        runs.append(best)
+        i = j
+    if len(runs) < nref:
+        return None
+    while len(runs) > nref:
+        k = min(range(len(runs)), key=lambda t: abs(err[runs[t]]))
+        if k == 0 or k == len(runs) - 1:
+            runs.pop(k)
+        elif len(runs) - nref == 1:
+            # drop the smaller end instead, which keeps the alternation
+            runs.pop(0 if abs(err[runs[0]]) < abs(err[runs[-1]]) else len(runs) - 1)
+        else:
+            nb = k - 1 if abs(err[runs[k - 1]]) < abs(err[runs[k + 1]]) else k + 1
+            for t in sorted((k, nb), reverse=True):
+                runs.pop(t)
+    return runs
+
+
+def remez_polish(n: int, N: int, b: int, A0, B0, M: int = 3000, iters: int = 25,
+                 verbose: bool = False):
+    """Polish a fit by Newton steps on the equioscillation conditions.
+
+    On a fixed dense grid of [0, z], take the 2N-1 alternating extrema of
+    err(x) = F~/F - 1 and solve err(x_i; p + dp) = (-1)^i E for dp and E (2N-1 unknowns:
+    the 2N-2 free parameters and the levelled error), with the derivative of err taken
+    through Q~.  Keeps the iterate with the smallest grid maximum.
+    """
+    mp.mp.prec = PREC
+    cn = consts(n)
+    z = cutoff(n, b)
+    X = z
+    par = Param(cn, N, X)
+    K = par.K
+    # free parameters from the expanded coefficients
+    p = [_mpf(0)] * K
+    for k in range(2, N):
+        p[k - 2] = A0[k] * X ** k
+    for k in range(1, N + 1):
+        p[(N - 2) + (k - 1)] = B0[k] * X ** k
+    xs = [X * (1 - mp.cos(mp.pi * (j + mp.mpf(1) / 2) / M)) / 2 for j in range(M)]
+    ts = [x / X for x in xs]
+    WQ = [exact_WQ(cn, x) for x in xs]
+    Ws = [w for w, _ in WQ]
+    PMt = [list(col) for col in zip(*par.PM)]
+    DLt = [list(col) for col in zip(*par.DL)]
+    s = cn.s
+
+    def errors(p):
+        P, D = par.coeffs(p)
+        out = []
+        der = []
+        for i, x in enumerate(xs):
+            Dv = _horner(D, ts[i])
+            if Dv <= 0:
+                return None, None
+            Qt = _horner(P, ts[i]) / Dv
+            if Qt <= 0:
+                return None, None
+            Wt = mp.exp(s * mp.log(Qt) - x)
+            e = mp.expm1(s * mp.log1p((Ws[i] - Wt) / (x + Wt)))
+            out.append(e)
+            der.append((-s * s * (1 + e) * Wt / ((x + Wt) * Qt), Dv, Qt))
+        return out, der
+
+    err, der = errors(p)
+    if err is None:
+        raise RuntimeError("starting point has a pole")
+    best = (max(abs(e) for e in err), list(p))
+    for it in range(iters):
+        idx = _alternation(err, K + 1)
+        if idx is None:
+            # one alternation short (the last extremum is pushed against z, where the
+            # weight vanishes): level the K extrema that exist, minimum-norm step
+            idx = _alternation(err, K)
+            if idx is None:
+                break
+        nr = len(idx)
+        sig = 1 if err[idx[0]] > 0 else -1
+        Mx = mp.matrix(nr, K + 1)
+        rhs = mp.matrix(nr, 1)
+        for r_, i in enumerate(idx):
+            dq, Dv, Qt = der[i]
+            row = [ts[i] ** k for k in range(N + 2)]
+            for j in range(K):
+                dP = mp.fdot(PMt[j], row[: N + 2])
+                dD = mp.fdot(DLt[j], row[: N + 1])
+                Mx[r_, j] = dq * (dP - Qt * dD) / Dv
+            Mx[r_, K] = -sig * (-1) ** r_
+            rhs[r_] = -err[i]
+        if nr == K + 1:
+            try:
+                sol = mp.lu_solve(Mx, rhs)
+            except ZeroDivisionError:
+                break
+            step = [sol[j] for j in range(K)]
+            # damped Newton: the step length with the smallest grid maximum
+            cand = None
+            lam = _mpf(1)
+            for _ in range(5):
+                trial = [p[j] + lam * step[j] for j in range(K)]
+                e2, d2 = errors(trial)
+                if e2 is not None:
+                    m2 = max(abs(e) for e in e2)
+                    if cand is None or m2 < cand[0]:
+                        cand = (m2, trial, e2, d2)
+                lam /= 2
+            if cand is None:
+                break
+            _, trial, e2, d2 = cand
+        else:
+            # K extrema for K parameters: level them at a target E below the current
+            # level (square system in dp) and keep the target that lowers the grid max
+            level = sum(abs(err[i]) for i in idx) / nr
+            Msq = mp.matrix(nr, K)
+            for r_ in range(nr):
+                for j in range(K):
+                    Msq[r_, j] = Mx[r_, j]
+            cand = None
+            for f in (0.97, 0.93, 0.85, 0.99, 0.75):
+                rh = mp.matrix(nr, 1)
+                for r_ in range(nr):
+                    rh[r_] = rhs[r_] - Mx[r_, K] * level * f
+                try:
+                    sol = mp.lu_solve(Msq, rh)
+                except ZeroDivisionError:
+                    continue
+                trial = [p[j] + sol[j] for j in range(K)]
+                e2, d2 = errors(trial)
+                if e2 is None:
+                    continue
+                m2 = max(abs(e) for e in e2)
+                if cand is None or m2 < cand[0]:
+                    cand = (m2, trial, e2, d2, f)
+            if cand is None:
+                break
+            _, trial, e2, d2, f = cand
+            sol = [_mpf(0)] * K + [level * f]
+        p, err, der = trial, e2, d2
+        emax = max(abs(e) for e in err)
+        if verbose:
+            print(f"remez n={n} N={N} b={b} it={it} eps={float(-mp.log(emax, 2)):.4f} "
+                  f"E={float(-mp.log(abs(sol[K]), 2)):.4f}", flush=True)
+        if emax < best[0]:
+            best = (emax, list(p))
+        elif it > 3 and emax > best[0] * 1.5:
+            break
+        if abs(emax / abs(sol[K]) - 1) < 1e-4:
+            break  # levelled
+    A, B = par.unscaled(best[1])
+    return A, B, float(-mp.log(best[0], 2))
 
 
 # ----------------------------------------------------------------------------------

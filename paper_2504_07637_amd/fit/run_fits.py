@@ -51,41 +51,25 @@ def table1_N(cls: str, n: int) -> int:
     return 4 if n <= 1 else 5 if n <= 9 else 6
 
 
-def _fit_one(job):
-    cls, n = job
-    mp.mp.prec = bf.PREC
-    b = 53 if cls == "fp64" else 24
-    N = table1_N(cls, n)
-    t0 = time.time()
-    attempts = [(500 if cls == "fp64" else 300, 1.0), (800, 1.0), (800, 1.1)]
-    last_err = None
-    for M, xs in attempts:
-        try:
-            r = bf.fit(n, N, b, M=M, iters=600 if cls == "fp64" else 300, X_scale=xs)
-            cn = bf.consts(n)
-            f = bf.factor(cn, r.A, r.B)
-            # no pole on [0, inf): every linear factor of v must have a negative root
-            if f.vl:
-                raise RuntimeError(f"v has real non-negative roots {f.vl}")
-            if r.B[-1] <= 0:
-                raise RuntimeError("B_N <= 0 (rejected, as in the paper)")
-            for y, a in f.uq + f.vq:
-                if a <= 0:
-                    raise RuntimeError("non-positive a in a quadratic factor")
-            fr = bf.round_factored(f, cls == "fp32")
-            eps_x = bf.dense_error(n, f, r.z, npts=1500)
-            eps_r = bf.dense_error(n, fr, r.z, npts=1500)
-            break
-        except Exception as exc:  # try the next sampling
-            last_err = exc
-            r = None
-    if r is None:
-        return {"cls": cls, "n": n, "N": N, "error": repr(last_err)}
+def _record_from(cls, n, N, b, A, B, z, t0, extra=None):
+    cn = bf.consts(n)
+    f = bf.factor(cn, A, B)
+    # no pole on [0, inf): every linear factor of v must have a negative root
+    if f.vl:
+        raise RuntimeError(f"v has real non-negative roots {f.vl}")
+    if B[-1] <= 0:
+        raise RuntimeError("B_N <= 0 (rejected, as in the paper)")
+    for y, a in f.uq + f.vq:
+        if a <= 0:
+            raise RuntimeError("non-positive a in a quadratic factor")
+    fr = bf.round_factored(f, cls == "fp32")
+    eps_x = bf.dense_error(n, f, z, npts=1500)
+    eps_r = bf.dense_error(n, fr, z, npts=1500)
     to_hex = bf.to_f32_hex if cls == "fp32" else (lambda v: bf.hexf(float(v)))
     rec = {
         "cls": cls, "n": n, "N": N, "b": b,
         "c": (bf.hexf(float(cn.c)), bf.decs(cn.c)),
-        "z": (bf.hexf(float(r.z)), bf.decs(r.z)),
+        "z": (bf.hexf(float(z)), bf.decs(z)),
         "q0": (to_hex(f.q0), bf.decs(f.q0)),
         "q1": (to_hex(f.q1), bf.decs(f.q1)),
         "q2": (to_hex(f.q2), bf.decs(f.q2)),
@@ -97,13 +81,86 @@ def _fit_one(job):
         "vq": [(to_hex(y), to_hex(a)) for y, a in f.vq],
         "vqx": [(bf.decs(y), bf.decs(a)) for y, a in f.vq],
         "vl": [to_hex(y) for y in f.vl], "vlx": [bf.decs(y) for y in f.vl],
-        "A": [bf.decs(a) for a in r.A], "B": [bf.decs(b_) for b_ in r.B],
-        "eps_exact": eps_x, "eps_rounded": eps_r, "eps_sampled": r.err_sampled,
-        "iterations": r.iterations, "seconds": time.time() - t0,
+        "A": [bf.decs(a) for a in A], "B": [bf.decs(b_) for b_ in B],
+        "eps_exact": eps_x, "eps_rounded": eps_r, "seconds": time.time() - t0,
     }
-    print(f"[fit] {cls} n={n} N={N} eps={eps_x:.2f} (rounded {eps_r:.2f}) "
+    if extra:
+        rec.update(extra)
+    return rec
+
+
+def _fit_one(job):
+    """Lawson-SK fit from scratch, then the Remez polish."""
+    cls, n = job
+    mp.mp.prec = bf.PREC
+    b = 53 if cls == "fp64" else 24
+    N = table1_N(cls, n)
+    t0 = time.time()
+    attempts = [(500 if cls == "fp64" else 300, 1.0), (800, 1.0), (800, 1.1)]
+    last_err = None
+    for M, xs in attempts:
+        try:
+            r = bf.fit(n, N, b, M=M, iters=600 if cls == "fp64" else 300, X_scale=xs)
+            A, B = r.A, r.B
+            try:
+                A2, B2, _ = bf.remez_polish(n, N, b, A, B)
+                A, B = A2, B2
+            except Exception:
+                pass
+            rec = _record_from(cls, n, N, b, A, B, r.z, t0,
+                               {"eps_sampled": r.err_sampled, "iterations": r.iterations})
+            break
+        except Exception as exc:  # try the next sampling
+            last_err = exc
+            rec = None
+    if rec is None:
+        return {"cls": cls, "n": n, "N": N, "error": repr(last_err)}
+    print(f"[fit] {cls} n={n} N={N} eps={rec['eps_exact']:.2f} (rounded {rec['eps_rounded']:.2f}) "
           f"{time.time() - t0:.0f}s", flush=True)
     return rec
+
+
+def _polish_one(job):
+    """Remez polish of an existing dataset entry; keeps the better of the two."""
+    cls, n, N, A, B, eps_old = job
+    mp.mp.prec = bf.PREC
+    b = 53 if cls == "fp64" else 24
+    t0 = time.time()
+    z = bf.cutoff(n, b)
+    A = [mp.mpf(a) for a in A]
+    B = [mp.mpf(v) for v in B]
+    best = None
+    try:
+        A2, B2, _ = bf.remez_polish(n, N, b, A, B, M=2000, iters=60)
+        best = _record_from(cls, n, N, b, A2, B2, z, t0)
+    except Exception as exc:
+        print(f"[polish] {cls} n={n} failed: {exc!r}", flush=True)
+    if best is None or best["eps_exact"] < eps_old:
+        best = _record_from(cls, n, N, b, A, B, z, t0)
+    print(f"[polish] {cls} n={n} N={N} eps {eps_old:.2f} -> {best['eps_exact']:.2f} "
+          f"(rounded {best['eps_rounded']:.2f}) {time.time() - t0:.0f}s", flush=True)
+    return best
+
+
+def read_expanded(path):
+    """(cls, n) -> (N, A decimal strings, B decimal strings, eps) from a dataset file."""
+    out = {}
+    cur = None
+    with open(path) as fh:
+        for raw in fh:
+            tok = raw.split("#", 1)[0].split()
+            if not tok:
+                continue
+            if tok[0] == "record":
+                cur = {"cls": tok[1], "n": int(tok[2]), "N": int(tok[3])}
+            elif tok[0] in ("A", "B") and cur is not None:
+                cur[tok[0]] = tok[2:]
+            elif tok[0] == "eps" and cur is not None:
+                cur["eps"] = float(tok[1])
+            elif tok[0] == "end":
+                out[(cur["cls"], cur["n"])] = cur
+                cur = None
+    return out
 
 
 def _line(tag, vals):
@@ -148,13 +205,23 @@ def main(argv=None):
     ap.add_argument("--classes", default="fp64,fp32")
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--report", default=REPORT)
+    ap.add_argument("--polish", action="store_true",
+                    help="polish the existing dataset at --out instead of fitting afresh")
     args = ap.parse_args(argv)
     classes = args.classes.split(",")
-    # long binary64 fits first so the pool drains evenly
-    jobs = [(c, n) for c in classes for n in range(args.nmax + 1)]
-    jobs.sort(key=lambda j: (j[0] != "fp64", -bf_cost(j)))
-    with mproc.Pool(args.jobs) as pool:
-        recs = pool.map(_fit_one, jobs, chunksize=1)
+    if args.polish:
+        old = read_expanded(args.out)
+        jobs = [(c, n, old[(c, n)]["N"], old[(c, n)]["A"], old[(c, n)]["B"], old[(c, n)]["eps"])
+                for c in classes for n in range(args.nmax + 1)]
+        jobs.sort(key=lambda j: -j[2])
+        with mproc.Pool(args.jobs) as pool:
+            recs = pool.map(_polish_one, jobs, chunksize=1)
+    else:
+        # long binary64 fits first so the pool drains evenly
+        jobs = [(c, n) for c in classes for n in range(args.nmax + 1)]
+        jobs.sort(key=lambda j: (j[0] != "fp64", -bf_cost(j)))
+        with mproc.Pool(args.jobs) as pool:
+            recs = pool.map(_fit_one, jobs, chunksize=1)
     bad = [r for r in recs if "error" in r]
     good = [r for r in recs if "error" not in r]
     write_dataset(good, args.out)

@@ -1,0 +1,105 @@
+"""Pins of the oracle's finite-precision evaluation of the approximant.
+
+Table 1 prints, for binary64 and binary32 arithmetic, the largest relative errors of F_0,
+F_{n-1} (from the downward recursion) and F_n (from the approximant) over ~2^20 evenly
+spaced points of [0, z_nb).  The oracle's binary64 evaluation, with re-fitted
+coefficients, must land within one bit of those numbers; a dropped term, a wrong index in
+the recursion or a wrong cut-off moves them by far more.  The mixed class (binary32
+rational and recursion, binary64 power) has no column of its own in the paper; it is held
+to the binary32 columns minus one bit.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+
+GRID = 1 << 16
+NS = [0, 1, 2, 3, 4, 7, 8, 11, 16, 20, 27, 36]
+
+
+def ebar(cls, n, rec=None, k=GRID):
+    r = rec if rec is not None else orc.record(cls, n)
+    x = np.arange(k) * (r["z"] / k)
+    A = orc.approx_f64(x, n, rec) if cls == "fp64" else orc.approx_mixed(x, n, rec)
+    A = A.astype(np.float64)
+    out = {}
+    for key, m in (("eb0", 0), ("ebn1", n - 1), ("ebn", n)):
+        if m < 0:
+            continue
+        hi, lo = orc.exact_one(x, m)
+        out[key] = orc.bits(orc.rel_err(A[m], hi, lo))
+    return out
+
+
+@pytest.mark.parametrize("n", NS)
+def test_binary64_finite_precision_error_matches_table1(n, table1):
+    got = ebar("fp64", n)
+    want = table1[n]["fp64"]
+    for key, v in got.items():
+        if want[key] is None:
+            continue
+        assert abs(v - want[key]) <= 1.0, (n, key, v, want[key])
+
+
+@pytest.mark.parametrize("n", NS)
+def test_mixed_class_at_least_the_binary32_columns(n, table1):
+    got = ebar("fp32", n)
+    want = table1[n]["fp32"]
+    for key, v in got.items():
+        if want[key] is None:
+            continue
+        assert v >= want[key] - 1.0, (n, key, v, want[key])
+
+
+def test_value_at_zero():
+    # F~_m(0) must be 1/(2m+1) to the accuracy of the approximant
+    for n in (0, 5, 16, 36):
+        F = orc.approx_f64(np.zeros(1), n)[:, 0]
+        want = 1.0 / (2 * np.arange(n + 1) + 1)
+        assert np.max(np.abs(F / want - 1)) < 2.0 ** -40
+
+
+def test_special_inputs():
+    x = np.array([-1.0, np.nan, np.inf, -0.0, 0.0])
+    for n in (0, 9):
+        F = orc.approx_f64(x, n)
+        G = orc.approx_mixed(x, n)
+        assert np.all(np.isnan(F[:, :2])) and np.all(np.isnan(G[:, :2]))
+        assert np.all(F[:, 2] == 0) and np.all(G[:, 2] == 0)
+        assert np.array_equal(F[:, 3], F[:, 4]) and np.array_equal(G[:, 3], G[:, 4])
+
+
+@pytest.mark.parametrize("cls,b", [("fp64", 53), ("fp32", 24)])
+def test_past_the_cutoff_and_large_arguments(cls, b):
+    # above z_nb every order is the long-range limit (Eq. limf1), accurate to about 2^-b
+    # plus the rounding of the upward product; far above, nothing under- or overflows early
+    for n in (0, 4, 16, 36):
+        z = orc.record(cls, n)["z"]
+        x = np.concatenate([np.nextafter(z, np.inf) * np.array([1.0, 1.0001, 1.5, 3.0]),
+                            [1e4, 1e8, 1e12, 1e30]])
+        A = (orc.approx_f64(x, n) if cls == "fp64" else orc.approx_mixed(x, n)).astype(float)
+        hi, lo = orc.exact(x, n)
+        for m in range(n + 1):
+            ok = np.abs(hi[m]) >= (2.2250738585072014e-308 if cls == "fp64"
+                                   else 1.1754943508222875e-38)
+            e = orc.rel_err(A[m][ok], hi[m][ok], lo[m][ok])
+            assert orc.bits(e) >= (b - 6), (cls, n, m, orc.bits(e))
+        assert A[0, -1] > 0  # F_0(1e30) = sqrt(pi)/2e15 is not lost to underflow
+
+
+def test_pin_detects_planted_mistakes():
+    # a wrong q1, or swapping the gathered factors of u and v, breaks the Table 1 pin
+    r = orc.record("fp64", 16)
+    ok = ebar("fp64", 16, r, k=1 << 12)
+    bad = orc.Record("fp64", 16, r.N)
+    bad.fields = dict(r.fields)
+    bad.fields["q1"] = r["q1"] * 1.0001
+    got = ebar("fp64", 16, bad, k=1 << 12)
+    assert got["ebn"] < ok["ebn"] - 8
+    swap = orc.Record("fp64", 16, r.N)
+    swap.fields = dict(r.fields)
+    swap.fields["ug"], swap.fields["vg"] = r["vg"], r["ug"]
+    got = ebar("fp64", 16, swap, k=1 << 12)
+    assert got["ebn"] < 20
