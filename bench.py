@@ -1,0 +1,238 @@
+"""Benchmark: Boys-function values per second on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+A step is one boys_eval call over the 2^26-argument integral workload (x = rho |PQ|^2,
+1% exact zeros) at n_max = 16: F_0..F_16 for every argument, binary64 (the headline) and
+the mixed binary32 class (reported beside it, with its speed-up).  Inputs are resident in
+HBM before the timed region.  Rank 0 prints one JSON line.
+
+Besides the headline the line carries:
+  roofline      HBM roofline of the dominant kernel (the binary64 n_max=16 kernel):
+                algorithmic bytes per launch (8 B read + 17 x 8 B written per argument)
+                over its average launch time from HIP events on the launch stream;
+                traffic from the committed rocprofv3 counter summary when it matches
+                the current kernel source, else null;
+  cpu_baseline  the CPU oracle's binary64 evaluation of the same approximant on a
+                bounded prefix of the same workload, on this host's cores;
+  accuracy      -log2 of the largest relative error per class against the exact
+                oracle on 2^13 sampled arguments (every m);
+  latency       p50/p99 of single calls on the small 65,536-argument workload
+                (n_max = 4, binary64), and the batched 8,192-array workload time.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+REPO = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, REPO)
+
+N_ARGS = 1 << 26
+N_MAX = 16
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(REPO, "profiles", "traffic_boys_f64_n16.json")
+KERNEL_SOURCES = [os.path.join(REPO, "paper_2504_07637_amd", "csrc", f)
+                  for f in ("boys_device.h", "boys_lib.hip", "boys_tables.inc")]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target length of the CPU-baseline sample")
+    ap.add_argument("--skip-extras", action="store_true",
+                    help="only the headline (for profiling runs)")
+    return ap.parse_args()
+
+
+def timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, e0.elapsed_time(e1) / 1e3
+
+
+def cpu_baseline(x, target_s):
+    from oracle import oracle as orc
+    threads = len(os.sched_getaffinity(0))
+    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
+    n = 1 << 18
+    while True:
+        t0 = time.perf_counter()
+        orc.approx_f64(x[:n], N_MAX)
+        dt = time.perf_counter() - t0
+        if dt * 4 > target_s or n * 4 > x.size:
+            break
+        n *= 4
+    return {"value": (N_MAX + 1) * n / dt, "unit": "values/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {n} arguments of the same 2^26 workload, n_max=16, binary64 "
+                      f"approximant oracle (plain C, OpenMP, {dt:.2f} s)"}
+
+
+def accuracy(torch, boys, xd, x):
+    from oracle import oracle as orc
+    g = np.random.default_rng(17)
+    idx = np.sort(g.choice(x.size, 1 << 13, replace=False))
+    ti = torch.from_numpy(idx).to(xd.device)
+    out = {}
+    hi, lo = orc.exact(x[idx], N_MAX)
+    for prec in ("fp64", "fp32"):
+        F = boys.boys_eval(xd, N_MAX, prec)[:, ti].double().cpu().numpy()
+        per_m = []
+        for m in range(N_MAX + 1):
+            ok = np.abs(hi[m]) >= 1.1754943508222875e-38
+            e = orc.rel_err(F[m][ok], hi[m][ok], lo[m][ok])
+            per_m.append(round(float(orc.bits(e)), 2))
+        out[prec] = {"bits_per_m": per_m, "min_bits": min(per_m)}
+        del F
+    return out
+
+
+def latency(torch, boys, inputs):
+    x = torch.from_numpy(inputs.uniform_mix(65536, seed=1)).to("cuda")
+    out = torch.empty((5, x.numel()), dtype=torch.float64, device="cuda")
+    for _ in range(20):
+        boys.boys_eval(x, 4, "fp64", out=out)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(1000):
+        t0 = time.perf_counter()
+        boys.boys_eval(x, 4, "fp64", out=out)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    ts = np.array(ts) * 1e6
+    return {"workload": "65,536 arguments (1/4 zeros, U[0,1], logU[1,50], logU[50,1e4]), "
+                        "n_max=4, binary64, call+synchronize",
+            "p50_us": round(float(np.percentile(ts, 50)), 2),
+            "p99_us": round(float(np.percentile(ts, 99)), 2)}
+
+
+def batched(torch, boys, inputs, steps):
+    plan_spec = inputs.batch_plan(8192, seed=4)
+    total = sum(l for l, _, _ in plan_spec)
+    xall = torch.from_numpy(inputs.integral_args(total, seed=4)).to("cuda")
+    xs, off = [], 0
+    for l, _, _ in plan_spec:
+        xs.append(xall[off:off + l])
+        off += l
+    nm = [m for _, m, _ in plan_spec]
+    pr = ["fp64" if p == 0 else "fp32" for _, _, p in plan_spec]
+    plan = boys.Plan(xs, nm, pr)
+    wall, gpu = timed(torch, plan.execute, steps, 2)
+    values = sum(l * (m + 1) for l, m, _ in plan_spec)
+    res = {"workload": "8,192 arrays, lengths logU[32,65536], n_max U{0..16}, "
+                       "binary64/binary32 alternating, one persistent graph launch",
+           "arguments": total, "ms": round(gpu / steps * 1e3, 4),
+           "values_per_s": values / (gpu / steps)}
+    plan.close()
+    return res
+
+
+def traffic_for(hash_now):
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != hash_now:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the path has no "
+                                   "cross-GPU step (arguments are independent)",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import torch
+
+    import paper_2504_07637_amd as boys
+    from paper_2504_07637_amd import inputs
+
+    x = inputs.integral_args(N_ARGS, seed=2)
+    xd = torch.from_numpy(x).to("cuda")
+    out64 = torch.empty((N_MAX + 1, N_ARGS), dtype=torch.float64, device="cuda")
+    out32 = torch.empty((N_MAX + 1, N_ARGS), dtype=torch.float32, device="cuda")
+
+    wall64, gpu64 = timed(torch, lambda: boys.boys_eval(xd, N_MAX, "fp64", out=out64),
+                          args.steps, args.warmup)
+    wall32, gpu32 = timed(torch, lambda: boys.boys_eval(xd, N_MAX, "fp32", out=out32),
+                          args.steps, args.warmup)
+    values = (N_MAX + 1) * N_ARGS
+    ms64 = wall64 / args.steps * 1e3
+    v64 = values * args.steps / wall64
+    v32 = values * args.steps / wall32
+    launch_s = gpu64 / args.steps
+    alg_bytes = (8 + 8 * (N_MAX + 1)) * N_ARGS
+    achieved = alg_bytes / launch_s / 1e9
+    khash = kernel_hash()
+    res = {
+        "metric": "F_m(x) values/s at n_max=16 FP64 vs FP32 (at stated err); p50/p99 latency",
+        "value": v64,
+        "unit": "values/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms64,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "integral-argument Boys evaluation: 2^26 x = rho|PQ|^2 "
+                               "(a,b logU[0.05,5e4], PQ ~ N(0, 2.0^2 I3), 1% zeros), "
+                               "F_0..F_16 binary64 SoA",
+                   "n_args": N_ARGS, "n_max": N_MAX},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_for(khash),
+                     "kernel": "k_plain<FP64,16>", "launch_ms": launch_s * 1e3,
+                     "alg_bytes_per_launch": alg_bytes, "kernel_hash": khash},
+        "fp32": {"value": v32, "unit": "values/s", "ms_per_step": wall32 / args.steps * 1e3,
+                 "speedup_vs_fp64": v32 / v64,
+                 "launch_ms": gpu32 / args.steps * 1e3,
+                 "hbm_GBs": (8 + 4 * (N_MAX + 1)) * N_ARGS / (gpu32 / args.steps) / 1e9},
+    }
+    del out32
+    torch.cuda.empty_cache()
+    if not args.skip_extras:
+        res["accuracy"] = accuracy(torch, boys, xd, x)
+        del out64
+        torch.cuda.empty_cache()
+        res["latency"] = latency(torch, boys, inputs)
+        res["batched"] = batched(torch, boys, inputs, max(3, args.steps // 2))
+        res["cpu_baseline"] = cpu_baseline(x, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,136 @@
+/*
+ * boys.h -- C ABI of libboys.so: bulk evaluation of the Boys functions on MI355X (gfx950).
+ *
+ * The Boys function of order m is F_m(x) = int_0^1 t^(2m) exp(-x t^2) dt, x >= 0
+ * (Laikov, arXiv 2504.07637, section "Introduction", Eq. fn).  The library evaluates
+ * F_m(x) for m = 0..n_max over arrays of arguments with the paper's global closed form
+ * (section "Methodology"):
+ *
+ *     F_n(x) = c_n / (x + Q~_n(x)^(n+1/2) exp(-x))^(n+1/2)             (Eq. fq)
+ *     Q~_n(x) = q0 + q1 x + q2 x^2 u_n(x) / v_n(x)                      (Eqs. pqz, pz, qz)
+ *     F_{m-1}(x) = (2x F_m(x) + exp(-x)) / (2m-1),  m = n..1             (Eq. r)
+ *     F_m(x) = c_m / x^(m+1/2) for x > z_nb                              (Eq. limf1, cut-off)
+ *
+ * with n = n_max and one exp(-x) shared by Eq. fq and Eq. r.  (The paper prints the
+ * divisor of Eq. r as 2m+1; integration by parts of Eq. fn gives 2m-1.)
+ *
+ * Conventions for every entry point:
+ *   - Pointers named x / out are DEVICE pointers (memory of the current HIP device);
+ *     all other pointers are host pointers.  The caller owns all of them; the library
+ *     never frees or retains them beyond the call (plans keep the pointers they were
+ *     given until updated or destroyed).
+ *   - x is binary64, contiguous, n elements.
+ *   - out holds (n_max + 1) rows of ld_out elements: F_m(x[i]) is at out[m * ld_out + i]
+ *     (structure of arrays), binary64 for BOYS_FP64 and binary32 for BOYS_FP32.
+ *     Requires ld_out >= n.  Alignment: 8 bytes (FP64) or 4 bytes (FP32); 256 bytes
+ *     gives the best store coalescing.
+ *   - stream is a hipStream_t (NULL = the null stream).  Calls only enqueue work and
+ *     return; results are ready when the stream reaches them.
+ *   - Inputs outside x >= 0: x < 0 or NaN gives NaN for every m; x = +inf gives 0.
+ *     x = -0.0 is treated as 0.
+ *   - Argument errors are detected on the host and returned before anything is
+ *     enqueued.  A failed kernel launch is reported as BOYS_ERR_DEVICE.  No C++
+ *     exception crosses this interface.  n == 0 is a successful no-op.
+ *   - Entry points are reentrant; a plan object must not be used from two threads at once.
+ */
+#ifndef BOYS_H
+#define BOYS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    /* binary64 throughout; output binary64 */
+    BOYS_FP64 = 0,
+    /* mixed class: u/v, Q~ and the power Q~^(n+1/2) and the recursion in binary32,
+       x + W and c_n / G^(n+1/2) in binary64 (the power whose rounding error is
+       amplified by n+1/2); output binary32 */
+    BOYS_FP32 = 1
+} boys_precision;
+
+typedef enum {
+    BOYS_OK = 0,
+    BOYS_ERR_INVALID_ARGUMENT = 1, /* null pointer with n > 0, ld_out < n, bad precision, count < 0 */
+    BOYS_ERR_UNSUPPORTED_NMAX = 2, /* n_max < 0 or n_max > boys_max_nmax(precision) */
+    BOYS_ERR_OUT_OF_MEMORY = 3,    /* a plan or batch could not get its device buffers */
+    BOYS_ERR_DEVICE = 4            /* a HIP call or kernel launch failed */
+} boys_status;
+
+/*
+ * Evaluate F_m(x[i]) for m = 0..n_max and i = 0..n-1 into out (layout above).
+ * precision is a boys_precision value.  The approximant of order n_max is used
+ * (coefficient set fitted for that n and that precision class, with the cut-off
+ * z_{n_max,b}, b = 53 for BOYS_FP64 and 24 for BOYS_FP32), and the lower orders come
+ * from the downward recursion of Eq. r below the cut-off and from Eq. limf1 above it.
+ */
+boys_status boys_eval(const double *x, int64_t n, int32_t n_max, void *out, int64_t ld_out,
+                      int32_t precision, void *stream);
+
+/* One argument array of a batch (host struct; x and out are device pointers). */
+typedef struct {
+    const double *x;
+    void *out;
+    int64_t n;
+    int64_t ld_out;
+    int32_t n_max;
+    int32_t precision;
+} boys_array;
+
+/* Launch parameters of the persistent batched kernel (0 in a field = library default). */
+typedef struct {
+    int32_t tile;        /* arguments per tile, a multiple of the block size */
+    int32_t block;       /* threads per workgroup: 64, 128, 256 (default) or 512 */
+    int32_t grid_per_cu; /* persistent workgroups per compute unit */
+    int32_t reserved;
+} boys_tuning;
+
+/*
+ * Evaluate every array of a batch in one persistent-kernel launch.  Results equal, bit
+ * for bit, those of boys_eval on each array alone.  arrays is a host array of count
+ * entries.  Builds a temporary schedule (device buffers allocated and freed inside the
+ * call, synchronising stream before the free); use a plan for repeated batches.
+ */
+boys_status boys_eval_batched(const boys_array *arrays, int32_t count, void *stream);
+
+/*
+ * Plans: a schedule (tiles ordered by decreasing cost, descriptor and tile tables in
+ * device memory, a work counter) and a HIP graph [reset counter, persistent kernel]
+ * built once for a batch and replayed by boys_plan_execute.  tuning may be NULL for the
+ * defaults.  boys_plan_update replaces the x/out pointers of a batch with the same
+ * count, lengths, n_max and precisions (other changes return BOYS_ERR_INVALID_ARGUMENT).
+ * A plan belongs to the device that was current at creation.
+ */
+typedef struct boys_plan boys_plan;
+boys_status boys_plan_create(boys_plan **plan, const boys_array *arrays, int32_t count,
+                             const boys_tuning *tuning);
+boys_status boys_plan_update(boys_plan *plan, const boys_array *arrays, int32_t count);
+boys_status boys_plan_execute(boys_plan *plan, void *stream);
+void boys_plan_destroy(boys_plan *plan);
+
+/*
+ * Autotuner: times plan execution for each of ncand candidate tunings on the given
+ * batch (each candidate executed warmup + reps times on stream, timed with HIP events)
+ * and writes the fastest into *best and, if times_ms is not NULL, the mean time of each
+ * candidate.  The arrays' out buffers are overwritten.
+ */
+boys_status boys_autotune(const boys_array *arrays, int32_t count, const boys_tuning *candidates,
+                          int32_t ncand, int32_t warmup, int32_t reps, void *stream,
+                          boys_tuning *best, float *times_ms);
+
+/* Largest supported n_max for a precision class (-1 for an unknown class). */
+int32_t boys_max_nmax(int32_t precision);
+
+/* The cut-off z_nb used for n_max = n in a precision class (NaN if unsupported). */
+double boys_cutoff(int32_t n, int32_t precision);
+
+/* Static description of a status code. */
+const char *boys_status_string(boys_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BOYS_H */

@@ -1,0 +1,184 @@
+"""Boys functions F_m(x), m = 0..n_max, on MI355X (gfx950) by Laikov's global closed form.
+
+Every computation runs in the HIP library libboys.so (include/boys.h); this module only
+allocates tensors with PyTorch, takes the current HIP stream and marshals arguments.
+
+    import torch, paper_2504_07637_amd as boys
+    x = torch.rand(1 << 20, dtype=torch.float64, device="cuda") * 40
+    F = boys.boys_eval(x, 16)                  # (17, 2^20) float64, F[m, i] = F_m(x[i])
+    G = boys.boys_eval(x, 16, precision="fp32")  # mixed class, float32 output
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import FP32, FP64, BoysArray, BoysError, BoysTuning
+
+__all__ = ["boys_eval", "boys_eval_batched", "Plan", "autotune", "max_nmax", "cutoff",
+           "precision_code", "BoysError", "FP64", "FP32"]
+
+
+def precision_code(precision) -> int:
+    if precision in (FP64, "fp64", "float64", "double"):
+        return FP64
+    if precision in (FP32, "fp32", "float32", "mixed"):
+        return FP32
+    raise ValueError(f"unknown precision {precision!r}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _out_dtype(code):
+    torch = _torch()
+    return torch.float64 if code == FP64 else torch.float32
+
+
+def _stream_ptr(stream, device):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_x(x):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.float64 or not x.is_cuda:
+        raise TypeError("x must be a float64 tensor on a HIP device")
+    if x.dim() != 1 or not x.is_contiguous():
+        raise ValueError("x must be 1-D and contiguous")
+
+
+def boys_eval(x, n_max: int, precision="fp64", out=None, stream=None):
+    """F_m(x) for m = 0..n_max as a (n_max+1, len(x)) tensor (row stride out.stride(0))."""
+    torch = _torch()
+    _check_x(x)
+    code = precision_code(precision)
+    n = x.numel()
+    if out is None:
+        out = torch.empty((n_max + 1, n), dtype=_out_dtype(code), device=x.device)
+    else:
+        if out.dtype != _out_dtype(code) or out.device != x.device or out.dim() != 2:
+            raise TypeError("out has the wrong dtype, device or rank")
+        if out.shape[0] != n_max + 1 or out.shape[1] != n or out.stride(1) != 1:
+            raise ValueError("out must be (n_max+1, n) with unit column stride")
+    ld = out.stride(0) if n > 0 else max(n, 1)
+    with torch.cuda.device(x.device):
+        st = _lib.lib().boys_eval(ctypes.c_void_p(x.data_ptr()), n, n_max,
+                                  ctypes.c_void_p(out.data_ptr()), ld, code,
+                                  _stream_ptr(stream, x.device))
+    _lib.check(st, "boys_eval")
+    return out
+
+
+def _arrays(xs, n_maxs, precisions, outs):
+    torch = _torch()
+    if not (len(xs) == len(n_maxs) == len(precisions)):
+        raise ValueError("xs, n_maxs and precisions differ in length")
+    if outs is None:
+        outs = [torch.empty((m + 1, x.numel()), dtype=_out_dtype(precision_code(p)),
+                            device=x.device) for x, m, p in zip(xs, n_maxs, precisions)]
+    arr = (BoysArray * max(1, len(xs)))()
+    for k, (x, m, p, o) in enumerate(zip(xs, n_maxs, precisions, outs)):
+        _check_x(x)
+        code = precision_code(p)
+        if o.dtype != _out_dtype(code) or o.shape[0] != m + 1 or o.shape[1] != x.numel():
+            raise ValueError(f"out[{k}] does not match its array")
+        arr[k].x = x.data_ptr()
+        arr[k].out = o.data_ptr()
+        arr[k].n = x.numel()
+        arr[k].ld_out = o.stride(0) if x.numel() > 0 else 1
+        arr[k].n_max = m
+        arr[k].precision = code
+    return arr, outs
+
+
+def boys_eval_batched(xs, n_maxs, precisions, outs=None, stream=None):
+    """Evaluate several arrays in one persistent launch; returns the list of outputs."""
+    torch = _torch()
+    arr, outs = _arrays(xs, n_maxs, precisions, outs)
+    dev = xs[0].device if xs else torch.device("cuda")
+    with torch.cuda.device(dev):
+        st = _lib.lib().boys_eval_batched(arr, len(xs), _stream_ptr(stream, dev))
+    _lib.check(st, "boys_eval_batched")
+    return outs
+
+
+def _tuning(t):
+    if t is None:
+        return None
+    if isinstance(t, BoysTuning):
+        return t
+    return BoysTuning(int(t.get("tile", 0)), int(t.get("block", 0)),
+                      int(t.get("grid_per_cu", 0)), 0)
+
+
+class Plan:
+    """A batched schedule captured in a HIP graph; execute() replays it."""
+
+    def __init__(self, xs, n_maxs, precisions, outs=None, tuning=None):
+        torch = _torch()
+        self._arr, self.outs = _arrays(xs, n_maxs, precisions, outs)
+        self._keep = (list(xs), list(self.outs))
+        self.device = xs[0].device if xs else torch.device("cuda")
+        self._p = ctypes.c_void_p()
+        t = _tuning(tuning)
+        with torch.cuda.device(self.device):
+            st = _lib.lib().boys_plan_create(ctypes.byref(self._p), self._arr, len(xs),
+                                             ctypes.byref(t) if t is not None else None)
+        _lib.check(st, "boys_plan_create")
+
+    def execute(self, stream=None):
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            st = _lib.lib().boys_plan_execute(self._p, _stream_ptr(stream, self.device))
+        _lib.check(st, "boys_plan_execute")
+        return self.outs
+
+    def update(self, xs, outs):
+        arr, outs = _arrays(xs, [a.n_max for a in self._arr[:len(xs)]],
+                            [a.precision for a in self._arr[:len(xs)]], outs)
+        st = _lib.lib().boys_plan_update(self._p, arr, len(xs))
+        _lib.check(st, "boys_plan_update")
+        self._arr, self.outs = arr, outs
+        self._keep = (list(xs), list(outs))
+
+    def close(self):
+        if self._p:
+            _lib.lib().boys_plan_destroy(self._p)
+            self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(xs, n_maxs, precisions, candidates, warmup=2, reps=5, stream=None):
+    """Time each candidate tuning (dicts with tile/block/grid_per_cu) on this batch.
+
+    Returns (best_tuning_dict, [ms per candidate])."""
+    torch = _torch()
+    arr, outs = _arrays(xs, n_maxs, precisions, None)
+    cand = (BoysTuning * len(candidates))(*[_tuning(c) for c in candidates])
+    best = BoysTuning()
+    times = (ctypes.c_float * len(candidates))()
+    dev = xs[0].device
+    with torch.cuda.device(dev):
+        st = _lib.lib().boys_autotune(arr, len(xs), cand, len(candidates), warmup, reps,
+                                      _stream_ptr(stream, dev), ctypes.byref(best), times)
+    _lib.check(st, "boys_autotune")
+    return ({"tile": best.tile, "block": best.block, "grid_per_cu": best.grid_per_cu},
+            list(times))
+
+
+def max_nmax(precision="fp64") -> int:
+    return int(_lib.lib().boys_max_nmax(precision_code(precision)))
+
+
+def cutoff(n: int, precision="fp64") -> float:
+    return float(_lib.lib().boys_cutoff(n, precision_code(precision)))

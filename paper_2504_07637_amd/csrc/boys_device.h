@@ -1,0 +1,299 @@
+// boys_device.h -- per-lane evaluation of the Boys functions F_0..F_n for gfx950.
+//
+// One lane evaluates one argument x.  For the order n = n_max (a compile-time constant,
+// so every loop below is unrolled and every coefficient is an immediate) the lane
+// computes, following Laikov, arXiv 2504.07637, section "Methodology":
+//
+//   e   = exp(-x)                                   correctly rounded binary64
+//   u,v = products of the factors of Eqs. pz, qz      (negative-real-part roots gathered
+//                                                     into one Horner polynomial)
+//   Q   = q0 + q1 x + q2 (u/v) x^2                   Eq. pqz
+//   W   = Q^n sqrt(Q) e,  G = x + W                   Eq. fq
+//   F_n = c_n / (G^n sqrt(G))                         Eq. fq
+//   F_{m-1} = (2x F_m + e) / (2m-1), m = n..1         Eq. r (divisor 2m-1, see below)
+//
+// and, past the cut-off x > z_nb, the long-range limit c_m / x^(m+1/2) of Eq. limf1 for
+// every m, generated upward from c_0 / sqrt(x).
+//
+// Arithmetic contract (the results are reproducible bit for bit on any IEEE machine
+// that follows the same steps):
+//   * every +, -, *, / and sqrt is a single correctly rounded IEEE operation; nothing is
+//     contracted into an fma except where an fma is written out;
+//   * exp(-x) is the correctly rounded binary64 value, computed in double-double
+//     (Tang's table method: a = k ln2/256 + r, 2^(j/256) from a table, a degree-8
+//     Taylor polynomial of exp(r)); the error before the last rounding is below 2^-95
+//     relative, so a misrounding needs exp(-x) within 2^-95 of a rounding boundary;
+//   * y^n is left-to-right binary powering, y^(n+1/2) = y^n * sqrt(y);
+//   * the recursion F_{m-1} = RN(RN(RN(2x) F_m) + e) / (2m-1)) divides by the odd
+//     constant d = 2m-1 as q = t*r, r = RN(1/d),
+//     q' = fma(fma(-q, d, t), r, q).  This is the correctly rounded t/d: the exact t/d
+//     is at least ulp/(2d) away from a rounding midpoint (t has a 53-bit or 24-bit
+//     significand and d is odd, so t/d cannot be a midpoint and differs from one by a
+//     multiple of ulp/(2d)), while q + (t - q d) r differs from t/d by less than
+//     2^-51 ulp.
+//
+// The recursion divisor: the paper prints Eq. r with 2m+1; integrating
+// d/dt (t^(2m-1) exp(-x t^2)) over [0, 1] gives exp(-x) = (2m-1) F_{m-1} - 2x F_m.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "boys_tables.inc"
+
+#pragma clang fp contract(off)
+
+namespace boys {
+
+// ---------------------------------------------------------------------------------
+// double-double helpers (error-free transformations)
+
+struct dd {
+    double hi, lo;
+};
+
+__host__ __device__ __forceinline__ dd two_prod(double a, double b)
+{
+    const double p = a * b;
+    return {p, __builtin_fma(a, b, -p)};
+}
+
+// requires |a| >= |b| (or a == 0)
+__host__ __device__ __forceinline__ dd fast_two_sum(double a, double b)
+{
+    const double s = a + b;
+    return {s, b - (s - a)};
+}
+
+__host__ __device__ __forceinline__ dd two_sum(double a, double b)
+{
+    const double s = a + b;
+    const double bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+
+// (a.hi + a.lo) * (b.hi + b.lo), relative error about 2^-104
+__host__ __device__ __forceinline__ dd mul_dd(dd a, dd b)
+{
+    dd p = two_prod(a.hi, b.hi);
+    double lo = __builtin_fma(a.hi, b.lo, p.lo);
+    lo = __builtin_fma(a.lo, b.hi, lo);
+    return fast_two_sum(p.hi, lo);
+}
+
+// a + b for |a.hi| >= |b.hi|
+__host__ __device__ __forceinline__ dd add_dd_fast(dd a, dd b)
+{
+    dd s = fast_two_sum(a.hi, b.hi);
+    const double lo = s.lo + (a.lo + b.lo);
+    return fast_two_sum(s.hi, lo);
+}
+
+// ---------------------------------------------------------------------------------
+// correctly rounded exp(a) for a in [-120, 0]
+//
+// tab: the 256 pairs (hi, lo) of 2^(j/256) (kept in LDS by the kernels).
+
+__host__ __device__ __forceinline__ double exp_rn(double a, const double2 *__restrict__ tab)
+{
+    using namespace boys_tab;
+    const double kd = __builtin_rint(a * kInvLn2x256);
+    const int k = (int)kd;
+    const int j = k & 255;
+    const int m = (k - j) / 256;
+    // r = a - k ln2/256 as a double-double; k * L1 is exact (L1 has 36 bits, |k| < 2^17)
+    const double t = __builtin_fma(-kd, kLn2d256_1, a);
+    const dd p2 = two_prod(kd, kLn2d256_2);
+    dd r = two_sum(t, -p2.hi);
+    r = fast_two_sum(r.hi, (r.lo - p2.lo) - kd * kLn2d256_3);
+    const double rh = r.hi;
+    // exp(r) - 1 = r + r^2 s2, s2 = 1/2 + r s3, s3 = 1/6 + r s4, s4 = 1/24 + r s5
+    const double s5 = kInvFact5_hi + rh * (kInvFact6_hi + rh * (kInvFact7_hi + rh * kInvFact8_hi));
+    dd s4 = fast_two_sum(kInvFact4_hi, rh * s5);
+    s4.lo += kInvFact4_lo;
+    const dd s3 = add_dd_fast(dd{kInvFact3_hi, kInvFact3_lo}, mul_dd(r, s4));
+    const dd s2 = add_dd_fast(dd{0.5, 0.0}, mul_dd(r, s3));
+    const dd pm1 = add_dd_fast(r, mul_dd(r, mul_dd(r, s2)));
+    // 2^(j/256) (1 + p)
+    const double2 T = tab[j];
+    dd q = two_prod(T.x, pm1.hi);
+    double lo = __builtin_fma(T.x, pm1.lo, q.lo);
+    lo = __builtin_fma(T.y, pm1.hi, lo);
+    lo = lo + T.y;
+    const dd s = fast_two_sum(T.x, q.hi);
+    const double v = s.hi + (s.lo + lo);
+    return __builtin_ldexp(v, m);
+}
+
+// ---------------------------------------------------------------------------------
+// small building blocks
+
+// y^K by left-to-right binary powering
+template <int K, typename T>
+__host__ __device__ __forceinline__ T powi(T y)
+{
+    if constexpr (K == 0) {
+        return T(1);
+    } else {
+        constexpr int top = 31 - __builtin_clz((unsigned)K);
+        T r = y;
+#pragma unroll
+        for (int b = top - 1; b >= 0; --b) {
+            r = r * r;
+            if ((K >> b) & 1)
+                r = r * y;
+        }
+        return r;
+    }
+}
+
+// RN(1/(2m-1)) for m = 1..kRcpSize-1, folded at compile time
+constexpr int kRcpSize = 64;
+struct OddReciprocals {
+    double d[kRcpSize];
+    float f[kRcpSize];
+    constexpr OddReciprocals() : d(), f()
+    {
+        for (int m = 1; m < kRcpSize; ++m) {
+            d[m] = 1.0 / (double)(2 * m - 1);
+            f[m] = 1.0f / (float)(2 * m - 1);
+        }
+    }
+};
+constexpr OddReciprocals kOddRcp{};
+
+// correctly rounded t / (2m-1) for a compile-time m (see the header comment)
+template <int M>
+__host__ __device__ __forceinline__ double div_odd(double t)
+{
+    static_assert(M >= 1 && M < kRcpSize, "recursion order out of range");
+    if constexpr (M == 1) {
+        return t;
+    } else {
+        constexpr double d = (double)(2 * M - 1);
+        constexpr double r = kOddRcp.d[M];
+        const double q = t * r;
+        const double rem = __builtin_fma(-q, d, t);
+        return __builtin_fma(rem, r, q);
+    }
+}
+
+template <int M>
+__host__ __device__ __forceinline__ float div_odd(float t)
+{
+    static_assert(M >= 1 && M < kRcpSize, "recursion order out of range");
+    if constexpr (M == 1) {
+        return t;
+    } else {
+        constexpr float d = (float)(2 * M - 1);
+        constexpr float r = kOddRcp.f[M];
+        const float q = t * r;
+        const float rem = __builtin_fmaf(-q, d, t);
+        return __builtin_fmaf(rem, r, q);
+    }
+}
+
+// downward recursion of Eq. r from F[M] to F[0], unrolled at compile time
+template <int M, typename T>
+__host__ __device__ __forceinline__ void recurse_down(T x2, T e, T f, T *F)
+{
+    if constexpr (M >= 1) {
+        const T g = div_odd<M>(x2 * f + e);
+        F[M - 1] = g;
+        recurse_down<M - 1, T>(x2, e, g, F);
+    }
+}
+
+// one of u, v: gathered monic polynomial (Horner), then quadratic, then linear factors
+template <typename T, int NG, int NQ, int NL>
+__host__ __device__ __forceinline__ T factors(T x, const T (&g)[NG > 0 ? NG : 1],
+                                              const T (&q)[NQ > 0 ? 2 * NQ : 1],
+                                              const T (&l)[NL > 0 ? NL : 1])
+{
+    T p = T(1);
+#pragma unroll
+    for (int k = NG - 1; k >= 0; --k)
+        p = p * x + g[k];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+        p = p * ((x - q[2 * k]) * (x - q[2 * k]) + q[2 * k + 1]);
+#pragma unroll
+    for (int k = 0; k < NL; ++k)
+        p = p * (x - l[k]);
+    return p;
+}
+
+// ---------------------------------------------------------------------------------
+// F_0..F_N for one argument, binary64 class
+
+template <int N>
+__host__ __device__ __forceinline__ void eval_f64(double x, const double2 *__restrict__ tab,
+                                                  double (&F)[N + 1])
+{
+    using S = boys_tab::F64Set<N>;
+    if (!(x > S::z)) {
+        // below the cut-off (NaN and negative x also pass here and are replaced below)
+        const double e = exp_rn(__builtin_fmax(-x, -120.0), tab);
+        const double u = factors<double, S::ug_n, S::uq_n, S::ul_n>(x, S::ug, S::uq, S::ul);
+        const double v = factors<double, S::vg_n, S::vq_n, S::vl_n>(x, S::vg, S::vq, S::vl);
+        const double Q = S::q0 + S::q1 * x + S::q2 * (u / v) * x * x;
+        const double W = powi<N>(Q) * __builtin_sqrt(Q) * e;
+        const double G = x + W;
+        const double f = S::c / (powi<N>(G) * __builtin_sqrt(G));
+        F[N] = f;
+        recurse_down<N, double>(2.0 * x, e, f, F);
+    } else {
+        // Eq. limf1 for every m; x = +inf gives 0 everywhere
+        const double ix = 1.0 / x;
+        double f = boys_tab::kC0 / __builtin_sqrt(x);
+        F[0] = f;
+#pragma unroll
+        for (int m = 1; m <= N; ++m) {
+            f = f * (m - 0.5) * ix;
+            F[m] = f;
+        }
+    }
+    if (!(x >= 0.0)) {
+#pragma unroll
+        for (int m = 0; m <= N; ++m)
+            F[m] = __builtin_nan("");
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// F_0..F_N for one argument, mixed binary32/binary64 class
+
+template <int N>
+__host__ __device__ __forceinline__ void eval_f32(double x, const double2 *__restrict__ tab,
+                                                  float (&F)[N + 1])
+{
+    using S = boys_tab::F32Set<N>;
+    if (!(x > S::z)) {
+        const float xf = (float)x;
+        const float e = (float)exp_rn(__builtin_fmax(-x, -120.0), tab);
+        const float u = factors<float, S::ug_n, S::uq_n, S::ul_n>(xf, S::ug, S::uq, S::ul);
+        const float v = factors<float, S::vg_n, S::vq_n, S::vl_n>(xf, S::vg, S::vq, S::vl);
+        const float Q = S::q0 + S::q1 * xf + S::q2 * (u / v) * xf * xf;
+        const float W = powi<N>(Q) * __builtin_sqrtf(Q) * e;
+        const double G = x + (double)W;
+        const float f = (float)(S::c / (powi<N>(G) * __builtin_sqrt(G)));
+        F[N] = f;
+        recurse_down<N, float>(2.0f * xf, e, f, F);
+    } else {
+        const double ix = 1.0 / x;
+        double f = boys_tab::kC0 / __builtin_sqrt(x);
+        F[0] = (float)f;
+#pragma unroll
+        for (int m = 1; m <= N; ++m) {
+            f = f * (m - 0.5) * ix;
+            F[m] = (float)f;
+        }
+    }
+    if (!(x >= 0.0)) {
+#pragma unroll
+        for (int m = 0; m <= N; ++m)
+            F[m] = __builtin_nanf("");
+    }
+}
+
+}  // namespace boys

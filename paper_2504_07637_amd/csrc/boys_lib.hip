@@ -1,0 +1,600 @@
+// boys_lib.hip -- kernels and C ABI of libboys.so (see include/boys.h).
+//
+// Kernels (gfx950, wave64):
+//   k_plain<C, N>    one lane per argument, grid-stride over the array; the exp table is
+//                    staged once per workgroup in LDS; x is read and the n_max+1 output
+//                    rows are written with coalesced non-temporal accesses (for a wave,
+//                    512 contiguous bytes per binary64 row).
+//   k_batched<MAXN>  persistent workgroups pull tiles from a device counter; a tile is
+//                    one slice of one array, so (precision, n_max) is uniform per tile and
+//                    the per-tile dispatch is a scalar branch to the same unrolled bodies
+//                    that k_plain uses, which makes batched results equal to solo ones
+//                    bit for bit.
+//   k_reset          zeroes the tile counter (a kernel rather than a memset node, so the
+//                    plan's graph replays correctly).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "boys.h"
+#include "boys_device.h"
+
+namespace {
+
+using boys_tab::kMaxN32;
+using boys_tab::kMaxN64;
+
+constexpr int kMaxN = kMaxN64 > kMaxN32 ? kMaxN64 : kMaxN32;
+
+// ---------------------------------------------------------------------------------
+// device code
+
+__device__ __forceinline__ void load_exp_table(double2 *tab)
+{
+    for (int t = threadIdx.x; t < 256; t += blockDim.x)
+        tab[t] = make_double2(boys_tab::kExp2Tab[2 * t], boys_tab::kExp2Tab[2 * t + 1]);
+    __syncthreads();
+}
+
+template <int N>
+__device__ __forceinline__ void body_f64(const double *__restrict__ x, double *__restrict__ out,
+                                         int64_t ld, int64_t i, const double2 *tab)
+{
+    double F[N + 1];
+    boys::eval_f64<N>(__builtin_nontemporal_load(x + i), tab, F);
+#pragma unroll
+    for (int m = 0; m <= N; ++m)
+        __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
+}
+
+template <int N>
+__device__ __forceinline__ void body_f32(const double *__restrict__ x, float *__restrict__ out,
+                                         int64_t ld, int64_t i, const double2 *tab)
+{
+    float F[N + 1];
+    boys::eval_f32<N>(__builtin_nontemporal_load(x + i), tab, F);
+#pragma unroll
+    for (int m = 0; m <= N; ++m)
+        __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
+}
+
+template <int C, int N>
+__global__ __launch_bounds__(256) void k_plain(const double *__restrict__ x, int64_t n,
+                                               void *__restrict__ out, int64_t ld)
+{
+    __shared__ double2 tab[256];
+    load_exp_table(tab);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if constexpr (C == BOYS_FP64)
+            body_f64<N>(x, static_cast<double *>(out), ld, i, tab);
+        else
+            body_f32<N>(x, static_cast<float *>(out), ld, i, tab);
+    }
+}
+
+struct Desc {
+    const double *x;
+    void *out;
+    int64_t n;
+    int64_t ld;
+    int32_t n_max;
+    int32_t prec;
+};
+
+template <int C, int N>
+__device__ __forceinline__ void tile_body(const Desc &d, int64_t start, int64_t cnt,
+                                          const double2 *tab)
+{
+    for (int64_t j = threadIdx.x; j < cnt; j += blockDim.x) {
+        if constexpr (C == BOYS_FP64)
+            body_f64<N>(d.x, static_cast<double *>(d.out), d.ld, start + j, tab);
+        else
+            body_f32<N>(d.x, static_cast<float *>(d.out), d.ld, start + j, tab);
+    }
+}
+
+// scalar dispatch over n (wave-uniform) to the unrolled bodies N = 0..MAXN
+template <int C, int N>
+__device__ __forceinline__ void dispatch_n(int n, const Desc &d, int64_t start, int64_t cnt,
+                                           const double2 *tab)
+{
+    if (n == N) {
+        tile_body<C, N>(d, start, cnt, tab);
+    } else if constexpr (N > 0) {
+        dispatch_n<C, N - 1>(n, d, start, cnt, tab);
+    }
+}
+
+template <int MAXN>
+__global__ __launch_bounds__(256) void k_batched(const Desc *__restrict__ descs,
+                                                 const int2 *__restrict__ tiles,
+                                                 int32_t ntiles, int32_t tile_args,
+                                                 uint32_t *__restrict__ counter)
+{
+    __shared__ double2 tab[256];
+    __shared__ int32_t s_tile;
+    load_exp_table(tab);
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_tile = (int32_t)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int32_t t = __builtin_amdgcn_readfirstlane(s_tile);
+        __syncthreads();
+        if (t >= ntiles)
+            break;
+        const int2 ts = tiles[t];
+        const int32_t a = __builtin_amdgcn_readfirstlane(ts.x);
+        const Desc d = descs[a];
+        const int64_t start = (int64_t)__builtin_amdgcn_readfirstlane(ts.y) * tile_args;
+        const int64_t rem = d.n - start;
+        const int64_t cnt = rem < tile_args ? rem : tile_args;
+        const int n = __builtin_amdgcn_readfirstlane(d.n_max);
+        if (__builtin_amdgcn_readfirstlane(d.prec) == BOYS_FP64)
+            dispatch_n<BOYS_FP64, (MAXN < kMaxN64 ? MAXN : kMaxN64)>(n, d, start, cnt, tab);
+        else
+            dispatch_n<BOYS_FP32, (MAXN < kMaxN32 ? MAXN : kMaxN32)>(n, d, start, cnt, tab);
+    }
+}
+
+__global__ void k_reset(uint32_t *counter)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *counter = 0u;
+}
+
+// ---------------------------------------------------------------------------------
+// host helpers
+
+int g_cu_count[64];
+std::once_flag g_cu_once[64];
+
+int cu_count()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 256;
+    std::call_once(g_cu_once[dev], [dev] {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            v <= 0)
+            v = 256;
+        g_cu_count[dev] = v;
+    });
+    return g_cu_count[dev];
+}
+
+using PlainLaunch = hipError_t (*)(const double *, int64_t, void *, int64_t, hipStream_t);
+
+template <int C, int N>
+hipError_t launch_plain(const double *x, int64_t n, void *out, int64_t ld, hipStream_t s)
+{
+    constexpr int kBlock = 256;
+    const int64_t need = (n + kBlock - 1) / kBlock;
+    const int64_t cap = (int64_t)cu_count() * 8;
+    const int grid = (int)std::max<int64_t>(1, std::min(need, cap));
+    hipLaunchKernelGGL((k_plain<C, N>), dim3(grid), dim3(kBlock), 0, s, x, n, out, ld);
+    return hipGetLastError();
+}
+
+template <int C, int... Ns>
+constexpr std::array<PlainLaunch, sizeof...(Ns)> plain_table(std::integer_sequence<int, Ns...>)
+{
+    return {&launch_plain<C, Ns>...};
+}
+
+const auto kPlain64 = plain_table<BOYS_FP64>(std::make_integer_sequence<int, kMaxN64 + 1>{});
+const auto kPlain32 = plain_table<BOYS_FP32>(std::make_integer_sequence<int, kMaxN32 + 1>{});
+
+int max_nmax(int32_t prec)
+{
+    if (prec == BOYS_FP64)
+        return kMaxN64;
+    if (prec == BOYS_FP32)
+        return kMaxN32;
+    return -1;
+}
+
+boys_status check_array(const double *x, int64_t n, int32_t n_max, const void *out,
+                        int64_t ld, int32_t prec)
+{
+    if (prec != BOYS_FP64 && prec != BOYS_FP32)
+        return BOYS_ERR_INVALID_ARGUMENT;
+    if (n < 0)
+        return BOYS_ERR_INVALID_ARGUMENT;
+    if (n_max < 0 || n_max > max_nmax(prec))
+        return BOYS_ERR_UNSUPPORTED_NMAX;
+    if (n == 0)
+        return BOYS_OK;
+    if (x == nullptr || out == nullptr || ld < n)
+        return BOYS_ERR_INVALID_ARGUMENT;
+    // the last output element must be addressable
+    const int64_t lim = INT64_MAX / 8;
+    if (ld > lim / (int64_t)(n_max + 1))
+        return BOYS_ERR_INVALID_ARGUMENT;
+    return BOYS_OK;
+}
+
+// buckets of the persistent kernel: the smallest MAXN >= the batch's largest n_max
+constexpr int kBuckets[] = {4, 8, 16, 24, kMaxN};
+using BatchedKernel = void (*)(const Desc *, const int2 *, int32_t, int32_t, uint32_t *);
+
+template <int MAXN>
+BatchedKernel batched_kernel()
+{
+    return &k_batched<MAXN>;
+}
+
+BatchedKernel pick_batched(int maxn)
+{
+    if (maxn <= kBuckets[0])
+        return batched_kernel<kBuckets[0]>();
+    if (maxn <= kBuckets[1])
+        return batched_kernel<kBuckets[1]>();
+    if (maxn <= kBuckets[2])
+        return batched_kernel<kBuckets[2]>();
+    if (maxn <= kBuckets[3])
+        return batched_kernel<kBuckets[3]>();
+    return batched_kernel<kBuckets[4]>();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------
+// plans
+
+struct boys_plan {
+    int device = 0;
+    int32_t count = 0;
+    std::vector<boys_array> arrays;   // shapes, for update checks
+    std::vector<Desc> host_desc;
+    Desc *d_desc = nullptr;
+    int2 *d_tiles = nullptr;
+    uint32_t *d_counter = nullptr;
+    int32_t ntiles = 0;
+    boys_tuning tuning{};
+    int grid = 0;
+    BatchedKernel kernel = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+constexpr int kDefaultTile = 2048;
+constexpr int kDefaultBlock = 256;
+constexpr int kDefaultGridPerCU = 4;
+
+boys_tuning resolve(const boys_tuning *t)
+{
+    boys_tuning r{kDefaultTile, kDefaultBlock, kDefaultGridPerCU, 0};
+    if (t) {
+        if (t->tile > 0)
+            r.tile = t->tile;
+        if (t->block > 0)
+            r.block = t->block;
+        if (t->grid_per_cu > 0)
+            r.grid_per_cu = t->grid_per_cu;
+    }
+    return r;
+}
+
+bool tuning_ok(const boys_tuning &t)
+{
+    const bool block_ok = t.block == 64 || t.block == 128 || t.block == 256;
+    return block_ok && t.tile >= t.block && t.tile % t.block == 0 && t.tile <= (1 << 24) &&
+           t.grid_per_cu >= 1 && t.grid_per_cu <= 64;
+}
+
+double tile_cost(const boys_array &a, int64_t cnt)
+{
+    const double bytes = 8.0 + (a.n_max + 1) * (a.precision == BOYS_FP64 ? 8.0 : 4.0);
+    return bytes * (double)cnt;
+}
+
+void free_plan_buffers(boys_plan *p)
+{
+    if (p->exec)
+        (void)hipGraphExecDestroy(p->exec);
+    if (p->graph)
+        (void)hipGraphDestroy(p->graph);
+    if (p->d_desc)
+        (void)hipFree(p->d_desc);
+    if (p->d_tiles)
+        (void)hipFree(p->d_tiles);
+    if (p->d_counter)
+        (void)hipFree(p->d_counter);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    p->d_desc = nullptr;
+    p->d_tiles = nullptr;
+    p->d_counter = nullptr;
+}
+
+boys_status build_schedule(boys_plan *p, const boys_array *arrays, int32_t count,
+                           std::vector<int2> &tiles)
+{
+    p->arrays.assign(arrays, arrays + count);
+    p->host_desc.resize(count);
+    struct T {
+        double cost;
+        int32_t array;
+        int32_t slice;
+    };
+    std::vector<T> all;
+    int maxn = 0;
+    for (int32_t a = 0; a < count; ++a) {
+        const boys_array &A = arrays[a];
+        p->host_desc[a] = Desc{A.x, A.out, A.n, A.ld_out, A.n_max, A.precision};
+        const int64_t nt = (A.n + p->tuning.tile - 1) / p->tuning.tile;
+        if (nt > INT32_MAX || (int64_t)all.size() + nt > INT32_MAX)
+            return BOYS_ERR_INVALID_ARGUMENT;
+        for (int64_t t = 0; t < nt; ++t) {
+            const int64_t cnt = std::min<int64_t>(p->tuning.tile, A.n - t * p->tuning.tile);
+            all.push_back({tile_cost(A, cnt), a, (int32_t)t});
+        }
+        if (A.n > 0)
+            maxn = std::max(maxn, A.n_max);
+    }
+    // longest processing time first; ties keep array order, so the tiles of one
+    // (precision, n_max) class run together and share the instruction cache
+    std::stable_sort(all.begin(), all.end(), [](const T &l, const T &r) { return l.cost > r.cost; });
+    tiles.resize(all.size());
+    for (size_t i = 0; i < all.size(); ++i)
+        tiles[i] = make_int2(all[i].array, all[i].slice);
+    p->kernel = pick_batched(maxn);
+    p->ntiles = (int32_t)all.size();
+    return BOYS_OK;
+}
+
+boys_status capture_graph(boys_plan *p)
+{
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+        return BOYS_ERR_DEVICE;
+    boys_status st = BOYS_OK;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return BOYS_ERR_DEVICE;
+    }
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, p->d_counter);
+    if (p->ntiles > 0)
+        hipLaunchKernelGGL(p->kernel, dim3(p->grid), dim3(p->tuning.block), 0, s, p->d_desc,
+                           p->d_tiles, p->ntiles, p->tuning.tile, p->d_counter);
+    if (hipGetLastError() != hipSuccess)
+        st = BOYS_ERR_DEVICE;
+    if (hipStreamEndCapture(s, &p->graph) != hipSuccess)
+        st = BOYS_ERR_DEVICE;
+    if (st == BOYS_OK && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+        st = BOYS_ERR_DEVICE;
+    (void)hipStreamDestroy(s);
+    return st;
+}
+
+boys_status validate_batch(const boys_array *arrays, int32_t count)
+{
+    if (count < 0 || (count > 0 && arrays == nullptr))
+        return BOYS_ERR_INVALID_ARGUMENT;
+    for (int32_t a = 0; a < count; ++a) {
+        const boys_array &A = arrays[a];
+        const boys_status st = check_array(A.x, A.n, A.n_max, A.out, A.ld_out, A.precision);
+        if (st != BOYS_OK)
+            return st;
+    }
+    return BOYS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+boys_status boys_eval(const double *x, int64_t n, int32_t n_max, void *out, int64_t ld_out,
+                      int32_t precision, void *stream)
+{
+    const boys_status st = check_array(x, n, n_max, out, ld_out, precision);
+    if (st != BOYS_OK || n == 0)
+        return st;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipError_t err = precision == BOYS_FP64 ? kPlain64[n_max](x, n, out, ld_out, s)
+                                                  : kPlain32[n_max](x, n, out, ld_out, s);
+    return err == hipSuccess ? BOYS_OK : BOYS_ERR_DEVICE;
+}
+
+boys_status boys_plan_create(boys_plan **plan, const boys_array *arrays, int32_t count,
+                             const boys_tuning *tuning)
+{
+    if (plan == nullptr)
+        return BOYS_ERR_INVALID_ARGUMENT;
+    *plan = nullptr;
+    boys_status st = validate_batch(arrays, count);
+    if (st != BOYS_OK)
+        return st;
+    const boys_tuning tn = resolve(tuning);
+    if (!tuning_ok(tn))
+        return BOYS_ERR_INVALID_ARGUMENT;
+    boys_plan *p = new (std::nothrow) boys_plan();
+    if (!p)
+        return BOYS_ERR_OUT_OF_MEMORY;
+    p->tuning = tn;
+    p->count = count;
+    (void)hipGetDevice(&p->device);
+    std::vector<int2> tiles;
+    st = build_schedule(p, arrays, count, tiles);
+    if (st != BOYS_OK) {
+        delete p;
+        return st;
+    }
+    p->grid = (int)std::max<int64_t>(
+        1, std::min<int64_t>((int64_t)cu_count() * tn.grid_per_cu, std::max(p->ntiles, 1)));
+    const size_t desc_bytes = sizeof(Desc) * std::max<int32_t>(count, 1);
+    const size_t tile_bytes = sizeof(int2) * std::max<int32_t>(p->ntiles, 1);
+    if (hipMalloc(&p->d_desc, desc_bytes) != hipSuccess ||
+        hipMalloc(&p->d_tiles, tile_bytes) != hipSuccess ||
+        hipMalloc(&p->d_counter, 256) != hipSuccess) {
+        (void)hipGetLastError();
+        free_plan_buffers(p);
+        delete p;
+        return BOYS_ERR_OUT_OF_MEMORY;
+    }
+    if ((count > 0 &&
+         hipMemcpy(p->d_desc, p->host_desc.data(), sizeof(Desc) * count, hipMemcpyHostToDevice) !=
+             hipSuccess) ||
+        (p->ntiles > 0 && hipMemcpy(p->d_tiles, tiles.data(), sizeof(int2) * p->ntiles,
+                                    hipMemcpyHostToDevice) != hipSuccess)) {
+        free_plan_buffers(p);
+        delete p;
+        return BOYS_ERR_DEVICE;
+    }
+    st = capture_graph(p);
+    if (st != BOYS_OK) {
+        free_plan_buffers(p);
+        delete p;
+        return st;
+    }
+    *plan = p;
+    return BOYS_OK;
+}
+
+boys_status boys_plan_update(boys_plan *p, const boys_array *arrays, int32_t count)
+{
+    if (p == nullptr || count != p->count)
+        return BOYS_ERR_INVALID_ARGUMENT;
+    boys_status st = validate_batch(arrays, count);
+    if (st != BOYS_OK)
+        return st;
+    for (int32_t a = 0; a < count; ++a) {
+        const boys_array &o = p->arrays[a], &A = arrays[a];
+        if (o.n != A.n || o.n_max != A.n_max || o.precision != A.precision)
+            return BOYS_ERR_INVALID_ARGUMENT;
+    }
+    for (int32_t a = 0; a < count; ++a) {
+        p->arrays[a] = arrays[a];
+        p->host_desc[a].x = arrays[a].x;
+        p->host_desc[a].out = arrays[a].out;
+        p->host_desc[a].ld = arrays[a].ld_out;
+    }
+    if (count > 0 && hipMemcpy(p->d_desc, p->host_desc.data(), sizeof(Desc) * count,
+                               hipMemcpyHostToDevice) != hipSuccess)
+        return BOYS_ERR_DEVICE;
+    return BOYS_OK;
+}
+
+boys_status boys_plan_execute(boys_plan *p, void *stream)
+{
+    if (p == nullptr)
+        return BOYS_ERR_INVALID_ARGUMENT;
+    if (hipGraphLaunch(p->exec, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return BOYS_ERR_DEVICE;
+    return BOYS_OK;
+}
+
+void boys_plan_destroy(boys_plan *p)
+{
+    if (p == nullptr)
+        return;
+    free_plan_buffers(p);
+    delete p;
+}
+
+boys_status boys_eval_batched(const boys_array *arrays, int32_t count, void *stream)
+{
+    boys_plan *p = nullptr;
+    boys_status st = boys_plan_create(&p, arrays, count, nullptr);
+    if (st != BOYS_OK)
+        return st;
+    st = boys_plan_execute(p, stream);
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess && st == BOYS_OK)
+        st = BOYS_ERR_DEVICE;
+    boys_plan_destroy(p);
+    return st;
+}
+
+boys_status boys_autotune(const boys_array *arrays, int32_t count, const boys_tuning *candidates,
+                          int32_t ncand, int32_t warmup, int32_t reps, void *stream,
+                          boys_tuning *best, float *times_ms)
+{
+    if (candidates == nullptr || ncand <= 0 || reps <= 0 || warmup < 0 || best == nullptr)
+        return BOYS_ERR_INVALID_ARGUMENT;
+    boys_status st = validate_batch(arrays, count);
+    if (st != BOYS_OK)
+        return st;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return BOYS_ERR_DEVICE;
+    float best_t = INFINITY;
+    int best_i = -1;
+    for (int32_t c = 0; c < ncand; ++c) {
+        float t_ms = INFINITY;
+        boys_plan *p = nullptr;
+        if (boys_plan_create(&p, arrays, count, &candidates[c]) == BOYS_OK) {
+            bool ok = true;
+            for (int32_t w = 0; w < warmup && ok; ++w)
+                ok = boys_plan_execute(p, stream) == BOYS_OK;
+            ok = ok && hipEventRecord(e0, s) == hipSuccess;
+            for (int32_t r = 0; r < reps && ok; ++r)
+                ok = boys_plan_execute(p, stream) == BOYS_OK;
+            ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+            float el = 0.f;
+            if (ok && hipEventElapsedTime(&el, e0, e1) == hipSuccess)
+                t_ms = el / reps;
+            boys_plan_destroy(p);
+        }
+        if (times_ms)
+            times_ms[c] = t_ms;
+        if (t_ms < best_t) {
+            best_t = t_ms;
+            best_i = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best_i < 0)
+        return BOYS_ERR_DEVICE;
+    *best = resolve(&candidates[best_i]);
+    return BOYS_OK;
+}
+
+int32_t boys_max_nmax(int32_t precision)
+{
+    return max_nmax(precision);
+}
+
+double boys_cutoff(int32_t n, int32_t precision)
+{
+    if (precision == BOYS_FP64 && n >= 0 && n <= kMaxN64)
+        return boys_tab::kCut64[n];
+    if (precision == BOYS_FP32 && n >= 0 && n <= kMaxN32)
+        return boys_tab::kCut32[n];
+    return NAN;
+}
+
+const char *boys_status_string(boys_status status)
+{
+    switch (status) {
+    case BOYS_OK:
+        return "ok";
+    case BOYS_ERR_INVALID_ARGUMENT:
+        return "invalid argument";
+    case BOYS_ERR_UNSUPPORTED_NMAX:
+        return "unsupported n_max";
+    case BOYS_ERR_OUT_OF_MEMORY:
+        return "out of device memory";
+    case BOYS_ERR_DEVICE:
+        return "device error";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,76 @@
+"""The C ABI: libboys.so loads, exports every function include/boys.h declares, and its
+host-side argument checks answer without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+REPO = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(REPO, "include", "boys.h")
+
+
+def _lib():
+    from paper_2504_07637_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libboys.so is not built (run __graft_entry__.build())")
+    return L
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(boys_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_binding_exports():
+    L = _lib()
+    assert declared_functions() == sorted(L.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_argument_errors_are_reported_before_any_launch():
+    L = _lib()
+    lib = L.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation
+    assert lib.boys_eval(None, 10, 4, fake, 10, L.FP64, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eval(fake, 10, 4, None, 10, L.FP64, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eval(fake, 10, 4, fake, 9, L.FP64, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eval(fake, -1, 4, fake, 10, L.FP64, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eval(fake, 10, 4, fake, 10, 7, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eval(fake, 10, -1, fake, 10, L.FP64, None) == L.ERR_UNSUPPORTED_NMAX
+    big = lib.boys_max_nmax(L.FP64) + 1
+    assert lib.boys_eval(fake, 10, big, fake, 10, L.FP64, None) == L.ERR_UNSUPPORTED_NMAX
+    # n == 0 is a successful no-op, whatever the pointers
+    assert lib.boys_eval(None, 0, 4, None, 0, L.FP32, None) == L.OK
+    p = ctypes.c_void_p()
+    assert lib.boys_plan_create(None, None, 0, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_plan_create(ctypes.byref(p), None, -1, None) == L.ERR_INVALID_ARGUMENT
+    arr = (L.BoysArray * 1)()
+    arr[0].x, arr[0].out, arr[0].n, arr[0].ld_out, arr[0].n_max, arr[0].precision = (
+        None, None, 5, 5, 2, L.FP64)
+    assert lib.boys_plan_create(ctypes.byref(p), arr, 1, None) == L.ERR_INVALID_ARGUMENT
+    bad = L.BoysTuning(100, 256, 4, 0)  # tile not a multiple of the block
+    arr[0].n = 0
+    assert lib.boys_plan_create(ctypes.byref(p), arr, 1, ctypes.byref(bad)) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_plan_execute(None, None) == L.ERR_INVALID_ARGUMENT
+    lib.boys_plan_destroy(None)
+
+
+def test_queries():
+    L = _lib()
+    lib = L.lib()
+    assert lib.boys_max_nmax(L.FP64) == 36 and lib.boys_max_nmax(L.FP32) == 36
+    assert lib.boys_max_nmax(9) == -1
+    assert abs(lib.boys_cutoff(16, L.FP64) - 74.5) < 0.1
+    assert abs(lib.boys_cutoff(16, L.FP32) - 47.6) < 0.1
+    assert lib.boys_cutoff(99, L.FP64) != lib.boys_cutoff(99, L.FP64)  # NaN
+    for s in range(5):
+        assert lib.boys_status_string(s)

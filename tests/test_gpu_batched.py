@@ -1,0 +1,113 @@
+"""GPU: the persistent batched launch and its plans (HIP graph replay, update, autotune).
+
+Invariant: every array's result in a batch is bit for bit the result of boys_eval on that
+array alone (the batched kernel runs the same unrolled bodies), and for a sample of arrays
+also identical to the CPU oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_common import report_mismatch, require_gpu, same_bits
+from oracle import oracle as orc
+from paper_2504_07637_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _batch(torch, count, seed, max_len=65536, nmax_hi=16):
+    spec = inputs.batch_plan(count, seed=seed, max_len=max_len, nmax_hi=nmax_hi)
+    total = sum(l for l, _, _ in spec)
+    x = inputs.integral_args(total, seed=seed + 1)
+    xd = torch.from_numpy(x).to("cuda")
+    xs, hs, off = [], [], 0
+    for l, _, _ in spec:
+        xs.append(xd[off:off + l])
+        hs.append(x[off:off + l])
+        off += l
+    nm = [m for _, m, _ in spec]
+    pr = ["fp64" if p == 0 else "fp32" for _, _, p in spec]
+    return xs, hs, nm, pr
+
+
+def _solo(boys, xs, nm, pr):
+    return [boys.boys_eval(x, m, p) for x, m, p in zip(xs, nm, pr)]
+
+
+def test_batched_equals_solo_and_oracle():
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    xs, hs, nm, pr = _batch(torch, 600, 40)
+    _say(f"[batched] 600 arrays, {sum(x.numel() for x in xs)} arguments")
+    outs = boys.boys_eval_batched(xs, nm, pr)
+    solo = _solo(boys, xs, nm, pr)
+    torch.cuda.synchronize()
+    for k, (o, s) in enumerate(zip(outs, solo)):
+        msg = report_mismatch(f"array {k}", o.cpu().numpy(), s.cpu().numpy())
+        assert not msg, msg
+    for k in range(0, 600, 37):
+        want = orc.approx_f64(hs[k], nm[k]) if pr[k] == "fp64" else orc.approx_mixed(hs[k], nm[k])
+        assert same_bits(outs[k].cpu().numpy(), want).all(), k
+
+
+def test_plan_graph_replays_and_update():
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    xs, hs, nm, pr = _batch(torch, 300, 50, nmax_hi=20)
+    solo = [s.cpu().numpy() for s in _solo(boys, xs, nm, pr)]
+    plan = boys.Plan(xs, nm, pr, tuning={"tile": 1024, "block": 256, "grid_per_cu": 2})
+    for rep in range(4):
+        _say(f"[plan] replay {rep}")
+        for o in plan.outs:
+            o.fill_(-1.0)
+        plan.execute()
+        # eager work and a synchronisation between replays
+        torch.ones(1 << 20, device="cuda").sum().item()
+        torch.cuda.synchronize()
+        for k, o in enumerate(plan.outs):
+            assert same_bits(o.cpu().numpy(), solo[k]).all(), (rep, k)
+    # new argument and output buffers with the same shapes
+    xs2 = [x.flip(0).contiguous() for x in xs]
+    outs2 = [torch.empty_like(o) for o in plan.outs]
+    plan.update(xs2, outs2)
+    plan.execute()
+    torch.cuda.synchronize()
+    solo2 = _solo(boys, xs2, nm, pr)
+    for k, (o, s) in enumerate(zip(plan.outs, solo2)):
+        assert same_bits(o.cpu().numpy(), s.cpu().numpy()).all(), k
+    plan.close()
+
+
+def test_full_batched_workload_equals_solo():
+    # the 8,192-array workload (lengths log-uniform in [32, 65536], n_max 0..16,
+    # binary64 and binary32 alternating) in one launch
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    xs, hs, nm, pr = _batch(torch, 8192, 4)
+    _say(f"[batched] 8192 arrays, {sum(x.numel() for x in xs)} arguments")
+    plan = boys.Plan(xs, nm, pr)
+    plan.execute()
+    torch.cuda.synchronize()
+    for k in range(0, 8192, 1):
+        s = boys.boys_eval(xs[k], nm[k], pr[k])
+        if not torch.equal(torch.nan_to_num(plan.outs[k]), torch.nan_to_num(s)):
+            pytest.fail(f"array {k} differs from its solo evaluation")
+    plan.close()
+
+
+def test_autotune_picks_a_candidate():
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    xs, hs, nm, pr = _batch(torch, 200, 60)
+    cands = [{"tile": 1024, "block": 256, "grid_per_cu": 2},
+             {"tile": 2048, "block": 256, "grid_per_cu": 4},
+             {"tile": 512, "block": 128, "grid_per_cu": 8}]
+    best, times = boys.autotune(xs, nm, pr, cands, warmup=1, reps=2)
+    assert best in cands and all(t > 0 for t in times)
+    assert times[cands.index(best)] == min(times)
