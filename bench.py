@@ -59,6 +59,9 @@ def parse():
                     help="target length of the CPU-baseline sample")
     ap.add_argument("--skip-extras", action="store_true",
                     help="only the headline (for profiling runs)")
+    ap.add_argument("--pmc-calibration", action="store_true",
+                    help="first copy 1 GiB device-to-device once, a dispatch of known "
+                         "traffic for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
     return ap.parse_args()
 
 
@@ -179,6 +182,12 @@ def main():
     import paper_2504_07637_amd as boys
     from paper_2504_07637_amd import inputs
 
+    if args.pmc_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     x = inputs.integral_args(N_ARGS, seed=2)
     xd = torch.from_numpy(x).to("cuda")
     out64 = torch.empty((N_MAX + 1, N_ARGS), dtype=torch.float64, device="cuda")

@@ -1,10 +1,13 @@
 // boys_lib.hip -- kernels and C ABI of libboys.so (see include/boys.h).
 //
 // Kernels (gfx950, wave64):
-//   k_plain<C, N>    one lane per argument, grid-stride over the array; the exp table is
-//                    staged once per workgroup in LDS; x is read and the n_max+1 output
-//                    rows are written with coalesced non-temporal accesses (for a wave,
-//                    512 contiguous bytes per binary64 row).
+//   k_plain<C, N, BS> one lane per argument, one argument per lane (a full grid: for the
+//                    (n_max+1)-row output this launch shape keeps the HBM write streams
+//                    densest); x is read and the output rows are written with coalesced
+//                    non-temporal accesses (for a wave, 512 contiguous bytes per binary64
+//                    row).  The binary64 class reads the 4 KiB exp table through the L1
+//                    cache with 128-thread workgroups; the mixed class stages it in LDS
+//                    with 256-thread workgroups (the faster shape for each, by measurement).
 //   k_batched<MAXN>  persistent workgroups pull tiles from a device counter; a tile is
 //                    one slice of one array, so (precision, n_max) is uniform per tile and
 //                    the per-tile dispatch is a scalar branch to the same unrolled bodies
@@ -66,14 +69,29 @@ __device__ __forceinline__ void body_f32(const double *__restrict__ x, float *__
         __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
 }
 
-template <int C, int N>
-__global__ __launch_bounds__(256) void k_plain(const double *__restrict__ x, int64_t n,
-                                               void *__restrict__ out, int64_t ld)
+// block size of the plain kernel per class
+template <int C>
+constexpr int plain_block()
 {
-    __shared__ double2 tab[256];
-    load_exp_table(tab);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    return C == BOYS_FP64 ? 128 : 256;
+}
+
+template <int C, int N>
+__global__ __launch_bounds__(plain_block<C>()) void k_plain(const double *__restrict__ x, int64_t n,
+                                                            void *__restrict__ out, int64_t ld)
+{
+    constexpr int BS = plain_block<C>();
+    const double2 *tab;
+    if constexpr (C == BOYS_FP64) {
+        tab = reinterpret_cast<const double2 *>(boys_tab::kExp2Tab);
+    } else {
+        __shared__ double2 lds_tab[256];
+        load_exp_table(lds_tab);
+        tab = lds_tab;
+    }
+    // one argument per lane for grids up to 2^31-1 workgroups; larger arrays stride
+    const int64_t stride = (int64_t)gridDim.x * BS;
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += stride) {
         if constexpr (C == BOYS_FP64)
             body_f64<N>(x, static_cast<double *>(out), ld, i, tab);
         else
@@ -177,10 +195,9 @@ using PlainLaunch = hipError_t (*)(const double *, int64_t, void *, int64_t, hip
 template <int C, int N>
 hipError_t launch_plain(const double *x, int64_t n, void *out, int64_t ld, hipStream_t s)
 {
-    constexpr int kBlock = 256;
+    constexpr int kBlock = plain_block<C>();
     const int64_t need = (n + kBlock - 1) / kBlock;
-    const int64_t cap = (int64_t)cu_count() * 8;
-    const int grid = (int)std::max<int64_t>(1, std::min(need, cap));
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, INT32_MAX));
     hipLaunchKernelGGL((k_plain<C, N>), dim3(grid), dim3(kBlock), 0, s, x, n, out, ld);
     return hipGetLastError();
 }
