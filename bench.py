@@ -60,8 +60,9 @@ def parse():
     ap.add_argument("--skip-extras", action="store_true",
                     help="only the headline (for profiling runs)")
     ap.add_argument("--pmc-calibration", action="store_true",
-                    help="first copy 1 GiB device-to-device once, a dispatch of known "
-                         "traffic for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
+                    help="first run one elementwise kernel over 1 GiB (1 GiB read, 1 GiB "
+                         "written), a dispatch of known traffic for scaling rocprofv3 "
+                         "FETCH_SIZE / WRITE_SIZE")
     return ap.parse_args()
 
 
@@ -183,9 +184,9 @@ def main():
     from paper_2504_07637_amd import inputs
 
     if args.pmc_calibration:
-        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.mul(a, 2.0, out=b)  # one elementwise kernel: 1 GiB read, 1 GiB written
         torch.cuda.synchronize()
         del a, b
     x = inputs.integral_args(N_ARGS, seed=2)
