@@ -18,7 +18,9 @@ Besides the headline the line carries:
   accuracy      -log2 of the largest relative error per class against the exact
                 oracle on 2^13 sampled arguments (every m);
   latency       p50/p99 of single calls on the small 65,536-argument workload
-                (n_max = 4, binary64), and the batched 8,192-array workload time.
+                (n_max = 4, binary64), and the batched 8,192-array workload time;
+  serving       p50/p99 request latency and sustained values/s of the serving loop
+                under Poisson arrivals at 20,000 requests/s.
 """
 from __future__ import annotations
 
@@ -160,6 +162,22 @@ def batched(torch, boys, inputs, steps):
     return res
 
 
+def serving(torch, duration=1.0):
+    from paper_2504_07637_amd import inputs
+    from paper_2504_07637_amd import serving as srv_mod
+    pool = srv_mod.argument_pool(1 << 24, seed=5)
+    reqs = inputs.serving_requests(rate=20000.0, duration=duration, seed=5)
+    with srv_mod.Server(budget_bytes=8 << 30, streams=4) as srv:
+        srv_mod.run_poisson(srv, reqs[:2000], pool)   # warm-up
+        res = srv_mod.run_poisson(srv, reqs, pool)
+    out = srv_mod.summarize(res)
+    out["workload"] = ("Poisson 20,000 requests/s, lengths logU[64,262144], n_max U{0..20}, "
+                       "binary64/binary32 50/50, integral-workload arguments, 8 GiB budget, "
+                       f"{duration:.1f} s; latency = completion - submission, host-to-device "
+                       "copies included")
+    return out
+
+
 def traffic_for(hash_now):
     try:
         with open(TRAFFIC_FILE) as fh:
@@ -240,6 +258,7 @@ def main():
         torch.cuda.empty_cache()
         res["latency"] = latency(torch, boys, inputs)
         res["batched"] = batched(torch, boys, inputs, max(3, args.steps // 2))
+        res["serving"] = serving(torch)
         res["cpu_baseline"] = cpu_baseline(x, args.cpu_seconds)
     print(json.dumps(res), flush=True)
 

@@ -82,9 +82,9 @@ typedef struct {
 /* Launch parameters of the persistent batched kernel (0 in a field = library default). */
 typedef struct {
     int32_t tile;        /* arguments per tile, a multiple of the block size */
-    int32_t block;       /* threads per workgroup: 64, 128, 256 (default) or 512 */
-    int32_t grid_per_cu; /* persistent workgroups per compute unit */
-    int32_t reserved;
+    int32_t block;       /* threads per workgroup: 64, 128 or 256 (default) */
+    int32_t grid_per_cu; /* persistent workgroups per compute unit (1..64) */
+    int32_t reserved;    /* must be 0 */
 } boys_tuning;
 
 /*
@@ -119,6 +119,62 @@ void boys_plan_destroy(boys_plan *plan);
 boys_status boys_autotune(const boys_array *arrays, int32_t count, const boys_tuning *candidates,
                           int32_t ncand, int32_t warmup, int32_t reps, void *stream,
                           boys_tuning *best, float *times_ms);
+
+/*
+ * Serving loop.  A server owns one device allocation of budget_bytes and a scheduler
+ * thread.  Each request is one argument array (host memory; pinned memory gives truly
+ * asynchronous copies), evaluated as by boys_eval into device memory owned by the server:
+ *   - requests are admitted in arrival order while their footprint (n*8 bytes for x plus
+ *     (n_max+1)*n*{8,4} bytes of output, each rounded up to 256 bytes) fits the budget;
+ *     one that does not fit waits until releases free enough memory;
+ *   - admitted requests are launched at the next opportunity: whenever one of the
+ *     `streams` execution slots is free, every admitted request not yet launched (up to
+ *     max_batch, and up to max_tiles tiles of `tile` arguments) goes out as one batched
+ *     persistent-kernel launch on that slot's stream; batches on different slots overlap
+ *     (continuous batching);
+ *   - a request completes when its batch's event completes; its output stays in device
+ *     memory (rows of ld = n elements) until boys_server_release.
+ * Times are seconds on the server's monotonic clock.  x_host must stay valid and
+ * unchanged until the request completes.  All functions are thread-safe.
+ */
+typedef struct boys_server boys_server;
+typedef struct {
+    int64_t budget_bytes; /* device memory for admitted requests (inputs + outputs) */
+    int32_t streams;      /* execution slots, one HIP stream each (0 = 4) */
+    int32_t max_batch;    /* requests per launch (0 = 256) */
+    int32_t tile;         /* arguments per tile, a multiple of 256 (0 = 2048) */
+    int32_t max_tiles;    /* tiles per launch (0 = 65536); larger requests are refused */
+} boys_server_config;
+typedef struct {
+    uint64_t submitted, admitted, launched, completed, released, batches;
+    uint64_t queued_now, inflight_now, max_queued, max_inflight;
+    uint64_t bytes_in_use, max_bytes_in_use;
+    uint64_t device_errors;
+} boys_server_stats;
+/* cfg is a host struct; the server is bound to the device current at creation. */
+boys_status boys_server_create(boys_server **server, const boys_server_config *cfg);
+/* BOYS_ERR_OUT_OF_MEMORY: the request can never fit (larger than the budget or the
+   per-launch tile capacity); BOYS_ERR_INVALID_ARGUMENT: n <= 0, null x_host, bad
+   precision; BOYS_ERR_UNSUPPORTED_NMAX as for boys_eval. */
+boys_status boys_server_submit(boys_server *server, const double *x_host, int64_t n,
+                               int32_t n_max, int32_t precision, uint64_t *id);
+/* Writes up to max ids of requests completed since the last poll; returns their count. */
+int32_t boys_server_poll(boys_server *server, uint64_t *ids, int32_t max);
+/* For a completed, unreleased request: device pointer of its output rows, their leading
+   dimension, and its submit and completion times. */
+boys_status boys_server_result(boys_server *server, uint64_t id, const void **out,
+                               int64_t *ld, double *t_submit, double *t_done);
+/* Copies a completed, unreleased request's (n_max+1) output rows into the device buffer
+   dst (row stride ld_dst >= n elements of the request's precision), enqueued on stream. */
+boys_status boys_server_copy_result(boys_server *server, uint64_t id, void *dst, int64_t ld_dst,
+                                    void *stream);
+/* Frees a completed request's device memory (its output pointer becomes invalid). */
+boys_status boys_server_release(boys_server *server, uint64_t id);
+boys_status boys_server_get_stats(boys_server *server, boys_server_stats *stats);
+/* Waits until nothing is queued or running (BOYS_ERR_DEVICE on timeout or device error). */
+boys_status boys_server_drain(boys_server *server, double timeout_s);
+/* Stops the scheduler, waits for the streams and frees everything. */
+void boys_server_destroy(boys_server *server);
 
 /* Largest supported n_max for a precision class (-1 for an unknown class). */
 int32_t boys_max_nmax(int32_t precision);

@@ -29,6 +29,15 @@ EXPORTS = (
     "boys_plan_execute",
     "boys_plan_destroy",
     "boys_autotune",
+    "boys_server_create",
+    "boys_server_submit",
+    "boys_server_poll",
+    "boys_server_result",
+    "boys_server_copy_result",
+    "boys_server_release",
+    "boys_server_get_stats",
+    "boys_server_drain",
+    "boys_server_destroy",
     "boys_max_nmax",
     "boys_cutoff",
     "boys_status_string",
@@ -44,6 +53,19 @@ class BoysArray(ctypes.Structure):
 class BoysTuning(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("grid_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class BoysServerConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("streams", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("max_tiles", ctypes.c_int32)]
+
+
+class BoysServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in (
+        "submitted", "admitted", "launched", "completed", "released", "batches",
+        "queued_now", "inflight_now", "max_queued", "max_inflight",
+        "bytes_in_use", "max_bytes_in_use", "device_errors")]
 
 
 class BoysError(RuntimeError):
@@ -81,6 +103,24 @@ def lib():
                                     i32, i32, i32, vp, ctypes.POINTER(BoysTuning),
                                     ctypes.POINTER(ctypes.c_float)]
         L.boys_autotune.restype = ctypes.c_int
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        dpp = ctypes.POINTER(ctypes.c_double)
+        L.boys_server_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(BoysServerConfig)]
+        L.boys_server_submit.argtypes = [vp, vp, i64, i32, i32, u64p]
+        L.boys_server_poll.argtypes = [vp, u64p, i32]
+        L.boys_server_poll.restype = i32
+        L.boys_server_result.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(vp),
+                                         ctypes.POINTER(i64), dpp, dpp]
+        L.boys_server_copy_result.argtypes = [vp, ctypes.c_uint64, vp, i64, vp]
+        L.boys_server_release.argtypes = [vp, ctypes.c_uint64]
+        L.boys_server_get_stats.argtypes = [vp, ctypes.POINTER(BoysServerStats)]
+        L.boys_server_drain.argtypes = [vp, ctypes.c_double]
+        L.boys_server_destroy.argtypes = [vp]
+        L.boys_server_destroy.restype = None
+        for f in (L.boys_server_create, L.boys_server_submit, L.boys_server_result,
+                  L.boys_server_copy_result, L.boys_server_release, L.boys_server_get_stats,
+                  L.boys_server_drain):
+            f.restype = ctypes.c_int
         L.boys_max_nmax.argtypes = [i32]
         L.boys_max_nmax.restype = i32
         L.boys_cutoff.argtypes = [i32, i32]

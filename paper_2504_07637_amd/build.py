@@ -3,7 +3,8 @@
     python -m paper_2504_07637_amd.build
 
 Steps: regenerate csrc/boys_tables.inc from data/boys_coeffs.txt, then one hipcc call
-that compiles csrc/boys_lib.hip into paper_2504_07637_amd/libboys.so.
+that compiles csrc/boys_lib.hip (kernels, plans) and csrc/boys_serve.hip (serving loop)
+into paper_2504_07637_amd/libboys.so.
 """
 from __future__ import annotations
 
@@ -54,7 +55,7 @@ def build_lib(verbose: bool = False) -> str:
     gen_tables()
     tmp = LIB + ".tmp"
     cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-o", tmp,
-           os.path.join(CSRC, "boys_lib.hip")]
+           os.path.join(CSRC, "boys_lib.hip"), os.path.join(CSRC, "boys_serve.hip"), "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -30,6 +30,7 @@
 
 #include "boys.h"
 #include "boys_device.h"
+#include "boys_internal.h"
 
 namespace {
 
@@ -101,14 +102,7 @@ __global__ __launch_bounds__(plain_block<C>()) void k_plain(const double *__rest
     }
 }
 
-struct Desc {
-    const double *x;
-    void *out;
-    int64_t n;
-    int64_t ld;
-    int32_t n_max;
-    int32_t prec;
-};
+using boys_internal::Desc;
 
 template <int C, int N>
 __device__ __forceinline__ void tile_body(const Desc &d, int64_t start, int64_t cnt,
@@ -274,6 +268,22 @@ BatchedKernel pick_batched(int maxn)
 }
 
 }  // namespace
+
+hipError_t boys_internal::launch_batched(const Desc *d_desc, const int2 *d_tiles, int32_t ntiles,
+                                         int32_t tile_args, uint32_t *d_counter, int maxn,
+                                         int grid, int block, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, d_counter);
+    if (ntiles > 0)
+        hipLaunchKernelGGL(pick_batched(maxn), dim3(grid), dim3(block), 0, s, d_desc, d_tiles,
+                           ntiles, tile_args, d_counter);
+    return hipGetLastError();
+}
+
+int boys_internal::cu_count()
+{
+    return ::cu_count();
+}
 
 // ---------------------------------------------------------------------------------
 // plans

@@ -1,0 +1,74 @@
+"""GPU: the serving loop (boys_server_*) under a Poisson stream of requests.
+
+Each checked request's result in the mix equals, bit for bit, boys_eval on the same
+arguments alone (the tolerance is 0: the batched launch runs the same kernels); every
+request completes; the device budget is respected; a small budget makes requests wait.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_common import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _check_kept(torch, boys, srv, reqs, pool, kept):
+    P = pool.numel()
+    for i, rid in kept.items():
+        ta, ln, nm, pr = reqs[i]
+        off = (i * 1000003) % (P - ln)
+        x = pool[off:off + ln].to("cuda")
+        solo = boys.boys_eval(x, nm, "fp64" if pr == 0 else "fp32")
+        got = srv.fetch(rid)
+        torch.cuda.synchronize()
+        assert torch.equal(got, solo), f"request {i} (n={ln}, n_max={nm}) differs from solo"
+        srv.release(rid)
+
+
+@pytest.mark.parametrize("budget_mb,streams", [(2048, 4), (64, 2)])
+def test_serving_results_equal_solo(budget_mb, streams):
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    from paper_2504_07637_amd import inputs, serving
+    pool = serving.argument_pool(1 << 22, seed=5)
+    reqs = inputs.serving_requests(rate=20000.0, duration=0.15, seed=55)
+    keep = set(range(0, len(reqs), 17))
+    _say(f"[serving] {len(reqs)} requests, budget {budget_mb} MiB, {streams} streams")
+    with serving.Server(budget_bytes=budget_mb << 20, streams=streams) as srv:
+        res = serving.run_poisson(srv, reqs, pool, keep=keep)
+        st = srv.stats()
+        _say(f"[serving] {serving.summarize(res)}")
+        assert st["completed"] == len(reqs) and st["device_errors"] == 0
+        assert st["max_bytes_in_use"] <= budget_mb << 20
+        if budget_mb == 64:
+            assert st["max_queued"] > 0
+        _check_kept(torch, boys, srv, reqs, pool, res["kept"])
+        assert srv.stats()["bytes_in_use"] == 0
+
+
+def test_serving_refuses_what_can_never_fit():
+    torch = require_gpu()
+    from paper_2504_07637_amd import serving
+    from paper_2504_07637_amd._lib import BoysError
+    with serving.Server(budget_bytes=16 << 20, streams=1) as srv:
+        x = torch.zeros(1 << 20, dtype=torch.float64).pin_memory()
+        with pytest.raises(BoysError):
+            srv.submit(x, 20, "fp64")          # 176 MB of output > 16 MB budget
+        with pytest.raises(BoysError):
+            srv.submit(x[:10], 99, "fp64")     # unsupported n_max
+        rid = srv.submit(x[:1000], 3, "fp32")
+        srv.drain(10.0)
+        assert srv.poll() == [rid]
+        out = srv.fetch(rid)
+        torch.cuda.synchronize()
+        from oracle import oracle as orc
+        want = orc.approx_mixed(np.zeros(1000), 3)
+        assert np.array_equal(out.cpu().numpy(), want)
+        srv.release(rid)
