@@ -129,7 +129,6 @@ struct boys_server {
     std::thread th;
     bool stop = false;
     std::chrono::steady_clock::time_point t0;
-    std::vector<hipError_t> teardown;
 };
 
 namespace {
@@ -371,7 +370,7 @@ boys_status boys_server_drain(boys_server *s, double timeout_s)
     for (;;) {
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            if (s->core->idle())
+            if (s->core->quiescent())
                 return s->ex.errors.load() ? BOYS_ERR_DEVICE : BOYS_OK;
         }
         if (std::chrono::steady_clock::now() > t_end)

@@ -270,6 +270,18 @@ class Core {
         return true;
     }
 
+    // nothing admitted and waiting for a slot, nothing running; requests may still be
+    // queued for memory (only releases by the client can admit them)
+    bool quiescent() const
+    {
+        if (!admitted_.empty())
+            return false;
+        for (auto &b : busy_)
+            if (!b.empty())
+                return false;
+        return true;
+    }
+
     bool idle() const
     {
         if (!queue_.empty() || !admitted_.empty())

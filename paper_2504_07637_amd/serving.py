@@ -91,7 +91,10 @@ class Server:
         return {k: int(getattr(s, k)) for k, _ in BoysServerStats._fields_}
 
     def drain(self, timeout_s: float = 60.0):
-        _lib.check(_lib.lib().boys_server_drain(self._s, timeout_s), "boys_server_drain")
+        """Wait until no admitted request is pending or running (queued ones may remain)."""
+        st = _lib.lib().boys_server_drain(self._s, timeout_s)
+        if st != _lib.OK:
+            raise _lib.BoysError(st, f"boys_server_drain (stats {self.stats()})")
 
     def close(self):
         if self._s:
@@ -164,8 +167,14 @@ def run_poisson(server: Server, requests, pool, keep=None, on_done=None):
             first_submit = now
         id2idx[rid] = i
         values += ln * (nm + 1)
-    server.drain(120.0)
-    collect()
+    # keep collecting (and releasing) until every request has completed: queued requests
+    # may be waiting for the memory that completed ones still hold
+    deadline = time.perf_counter() + 120.0
+    while len(lat) < len(requests):
+        server.drain(120.0)
+        collect()
+        if time.perf_counter() > deadline:
+            raise RuntimeError(f"serving stalled: {server.stats()}")
     t_end = time.perf_counter() - t0
     lats = np.array([lat[i] for i in sorted(lat)])
     return {"latencies": lats, "lag": np.array(lag), "values": values,
