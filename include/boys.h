@@ -171,10 +171,11 @@ boys_status boys_server_copy_result(boys_server *server, uint64_t id, void *dst,
 /* Frees a completed request's device memory (its output pointer becomes invalid). */
 boys_status boys_server_release(boys_server *server, uint64_t id);
 boys_status boys_server_get_stats(boys_server *server, boys_server_stats *stats);
-/* Waits until no admitted request is waiting for a slot or running.  Requests still
-   queued for memory stay queued: only releases of completed requests can admit them, so
-   a client that holds results must keep polling and releasing (BOYS_ERR_DEVICE on timeout
-   or after a device error). */
+/* Waits until no admitted request is waiting for a slot or running and the queue is
+   empty or its head does not fit the free memory.  Requests still queued for memory stay
+   queued: only releases of completed requests can admit them, so a client that holds
+   results must keep polling and releasing (BOYS_ERR_DEVICE on timeout or after a device
+   error). */
 boys_status boys_server_drain(boys_server *server, double timeout_s);
 /* Stops the scheduler, waits for the streams and frees everything. */
 void boys_server_destroy(boys_server *server);

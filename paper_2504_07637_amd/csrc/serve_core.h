@@ -270,8 +270,8 @@ class Core {
         return true;
     }
 
-    // nothing admitted and waiting for a slot, nothing running; requests may still be
-    // queued for memory (only releases by the client can admit them)
+    // nothing admitted and waiting for a slot, nothing running, and the queue is empty
+    // or its head does not fit the free memory (only releases by the client can admit it)
     bool quiescent() const
     {
         if (!admitted_.empty())
@@ -279,7 +279,10 @@ class Core {
         for (auto &b : busy_)
             if (!b.empty())
                 return false;
-        return true;
+        if (queue_.empty())
+            return true;
+        const Request &head = reqs_.at(queue_.front());
+        return pool_.largest_free() < align_up(head.bytes);
     }
 
     bool idle() const
