@@ -79,16 +79,22 @@ typedef struct {
     int32_t precision;
 } boys_array;
 
-/* Launch parameters of the persistent batched kernel (0 in a field = library default). */
+/*
+ * Launch parameters of a batched launch (0 in tile/block/grid_per_cu = library default).
+ * schedule 0: persistent workgroups (grid_per_cu per compute unit) take tiles from a work
+ *             counter in longest-first order;
+ * schedule 1: one workgroup per tile, dispatched by the hardware in longest-first order;
+ *             tile must be block x 1, 2, 4 or 8.
+ */
 typedef struct {
     int32_t tile;        /* arguments per tile, a multiple of the block size */
-    int32_t block;       /* threads per workgroup: 64, 128 or 256 (default) */
-    int32_t grid_per_cu; /* persistent workgroups per compute unit (1..64) */
-    int32_t reserved;    /* must be 0 */
+    int32_t block;       /* threads per workgroup: 64, 128 or 256 */
+    int32_t grid_per_cu; /* schedule 0: persistent workgroups per compute unit (1..64) */
+    int32_t schedule;    /* 0 or 1 (above) */
 } boys_tuning;
 
 /*
- * Evaluate every array of a batch in one persistent-kernel launch.  Results equal, bit
+ * Evaluate every array of a batch in one batched launch.  Results equal, bit
  * for bit, those of boys_eval on each array alone.  arrays is a host array of count
  * entries.  Builds a temporary schedule (device buffers allocated and freed inside the
  * call, synchronising stream before the free); use a plan for repeated batches.
@@ -97,8 +103,9 @@ boys_status boys_eval_batched(const boys_array *arrays, int32_t count, void *str
 
 /*
  * Plans: a schedule (tiles ordered by decreasing cost, descriptor and tile tables in
- * device memory, a work counter) and a HIP graph [reset counter, persistent kernel]
- * built once for a batch and replayed by boys_plan_execute.  tuning may be NULL for the
+ * device memory, a work counter) and a HIP graph of the batched launch (schedule 0:
+ * [reset counter, persistent kernel]; schedule 1: [one workgroup per tile]) built once
+ * for a batch and replayed by boys_plan_execute.  tuning may be NULL for the
  * defaults.  boys_plan_update replaces the x/out pointers of a batch with the same
  * count, lengths, n_max and precisions (other changes return BOYS_ERR_INVALID_ARGUMENT).
  * A plan belongs to the device that was current at creation.
@@ -130,7 +137,7 @@ boys_status boys_autotune(const boys_array *arrays, int32_t count, const boys_tu
  *   - admitted requests are launched at the next opportunity: whenever one of the
  *     `streams` execution slots is free, every admitted request not yet launched (up to
  *     max_batch, and up to max_tiles tiles of `tile` arguments) goes out as one batched
- *     persistent-kernel launch on that slot's stream; batches on different slots overlap
+ *     launch on that slot's stream; batches on different slots overlap
  *     (continuous batching);
  *   - a request completes when its batch's event completes; its output stays in device
  *     memory (rows of ld = n elements) until boys_server_release.
@@ -142,7 +149,8 @@ typedef struct {
     int64_t budget_bytes; /* device memory for admitted requests (inputs + outputs) */
     int32_t streams;      /* execution slots, one HIP stream each (0 = 4) */
     int32_t max_batch;    /* requests per launch (0 = 256) */
-    int32_t tile;         /* arguments per tile, a multiple of 256 (0 = 2048) */
+    int32_t tile;         /* arguments per tile: 256, 512, 1024 or 2048 (0 = 256); one
+                             256-thread workgroup per tile */
     int32_t max_tiles;    /* tiles per launch (0 = 65536); larger requests are refused */
 } boys_server_config;
 typedef struct {

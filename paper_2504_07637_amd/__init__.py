@@ -113,7 +113,7 @@ def _tuning(t):
     if isinstance(t, BoysTuning):
         return t
     return BoysTuning(int(t.get("tile", 0)), int(t.get("block", 0)),
-                      int(t.get("grid_per_cu", 0)), 0)
+                      int(t.get("grid_per_cu", 0)), int(t.get("schedule", 1)))
 
 
 class Plan:
@@ -159,7 +159,7 @@ class Plan:
 
 
 def autotune(xs, n_maxs, precisions, candidates, warmup=2, reps=5, stream=None):
-    """Time each candidate tuning (dicts with tile/block/grid_per_cu) on this batch.
+    """Time each candidate tuning (dicts with tile/block/grid_per_cu/schedule) on this batch.
 
     Returns (best_tuning_dict, [ms per candidate])."""
     torch = _torch()
@@ -172,8 +172,8 @@ def autotune(xs, n_maxs, precisions, candidates, warmup=2, reps=5, stream=None):
         st = _lib.lib().boys_autotune(arr, len(xs), cand, len(candidates), warmup, reps,
                                       _stream_ptr(stream, dev), ctypes.byref(best), times)
     _lib.check(st, "boys_autotune")
-    return ({"tile": best.tile, "block": best.block, "grid_per_cu": best.grid_per_cu},
-            list(times))
+    return ({"tile": best.tile, "block": best.block, "grid_per_cu": best.grid_per_cu,
+             "schedule": best.schedule}, list(times))
 
 
 def max_nmax(precision="fp64") -> int:

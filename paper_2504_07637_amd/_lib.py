@@ -52,7 +52,7 @@ class BoysArray(ctypes.Structure):
 
 class BoysTuning(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("grid_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("grid_per_cu", ctypes.c_int32), ("schedule", ctypes.c_int32)]
 
 
 class BoysServerConfig(ctypes.Structure):

@@ -17,12 +17,20 @@ struct Desc {
     int32_t prec;
 };
 
-// Enqueue [zero the counter, persistent batched kernel] on stream s.  tiles holds
-// (array index, slice index) pairs; slice k of array a covers arguments
-// [k * tile_args, min((k+1) * tile_args, n_a)).  maxn is the largest n_max in the batch.
+// how a batch is launched
+struct Launch {
+    int schedule;  // 0: persistent workgroups + work counter; 1: one workgroup per tile
+    int tile;      // arguments per tile (schedule 1: block x 1, 2, 4 or 8)
+    int block;     // threads per workgroup (64, 128, 256)
+    int grid;      // schedule 0: number of persistent workgroups
+};
+
+// Enqueue a batch on stream s: schedule 0 = [zero the counter, persistent kernel],
+// schedule 1 = [one workgroup per tile].  tiles holds (array index, slice index) pairs;
+// slice k of array a covers arguments [k * tile, min((k+1) * tile, n_a)).  maxn is the
+// largest n_max in the batch.
 hipError_t launch_batched(const Desc *d_desc, const int2 *d_tiles, int32_t ntiles,
-                          int32_t tile_args, uint32_t *d_counter, int maxn, int grid,
-                          int block, hipStream_t s);
+                          uint32_t *d_counter, int maxn, const Launch &L, hipStream_t s);
 
 int cu_count();
 

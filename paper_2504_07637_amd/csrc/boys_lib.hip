@@ -159,6 +159,57 @@ __global__ __launch_bounds__(256) void k_batched(const Desc *__restrict__ descs,
     }
 }
 
+// K guarded iterations, fully unrolled (no loop): a tile of K * blockDim arguments
+template <int C, int N, int K>
+__device__ __forceinline__ void tile_body_unrolled(const Desc &d, int64_t start,
+                                                   const double2 *tab)
+{
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        const int64_t i = start + (int64_t)a * blockDim.x + threadIdx.x;
+        if (i < d.n) {
+            if constexpr (C == BOYS_FP64)
+                body_f64<N>(d.x, static_cast<double *>(d.out), d.ld, i, tab);
+            else
+                body_f32<N>(d.x, static_cast<float *>(d.out), d.ld, i, tab);
+        }
+    }
+}
+
+template <int C, int N, int K>
+__device__ __forceinline__ void dispatch_wg(int n, const Desc &d, int64_t start,
+                                            const double2 *tab)
+{
+    if (n == N) {
+        tile_body_unrolled<C, N, K>(d, start, tab);
+    } else if constexpr (N > 0) {
+        dispatch_wg<C, N - 1, K>(n, d, start, tab);
+    }
+}
+
+// one workgroup per tile: the hardware dispatcher hands out the tiles in table order
+// (longest first), no work counter; binary64 bodies read the exp table through L1,
+// binary32 bodies stage it in LDS, as the plain kernels do
+template <int MAXN, int K>
+__global__ __launch_bounds__(256) void k_batched_wg(const Desc *__restrict__ descs,
+                                                    const int2 *__restrict__ tiles,
+                                                    int32_t tile_args)
+{
+    __shared__ double2 lds_tab[256];
+    const int2 ts = tiles[blockIdx.x];
+    const int32_t a = __builtin_amdgcn_readfirstlane(ts.x);
+    const Desc d = descs[a];
+    const int64_t start = (int64_t)__builtin_amdgcn_readfirstlane(ts.y) * tile_args;
+    const int n = __builtin_amdgcn_readfirstlane(d.n_max);
+    if (__builtin_amdgcn_readfirstlane(d.prec) == BOYS_FP64) {
+        dispatch_wg<BOYS_FP64, (MAXN < kMaxN64 ? MAXN : kMaxN64), K>(
+            n, d, start, reinterpret_cast<const double2 *>(boys_tab::kExp2Tab));
+    } else {
+        load_exp_table(lds_tab);
+        dispatch_wg<BOYS_FP32, (MAXN < kMaxN32 ? MAXN : kMaxN32), K>(n, d, start, lds_tab);
+    }
+}
+
 __global__ void k_reset(uint32_t *counter)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0)
@@ -244,39 +295,63 @@ boys_status check_array(const double *x, int64_t n, int32_t n_max, const void *o
     return BOYS_OK;
 }
 
-// buckets of the persistent kernel: the smallest MAXN >= the batch's largest n_max
+// buckets of the batched kernels: the smallest MAXN >= the batch's largest n_max
 constexpr int kBuckets[] = {4, 8, 16, 24, kMaxN};
-using BatchedKernel = void (*)(const Desc *, const int2 *, int32_t, int32_t, uint32_t *);
+constexpr int kNumBuckets = 5;
+using PersistentKernel = void (*)(const Desc *, const int2 *, int32_t, int32_t, uint32_t *);
+using WgKernel = void (*)(const Desc *, const int2 *, int32_t);
 
-template <int MAXN>
-BatchedKernel batched_kernel()
+int bucket_of(int maxn)
 {
-    return &k_batched<MAXN>;
+    for (int b = 0; b < kNumBuckets; ++b)
+        if (maxn <= kBuckets[b])
+            return b;
+    return kNumBuckets - 1;
 }
 
-BatchedKernel pick_batched(int maxn)
+template <int... B>
+constexpr std::array<PersistentKernel, sizeof...(B)> persistent_table(std::integer_sequence<int, B...>)
 {
-    if (maxn <= kBuckets[0])
-        return batched_kernel<kBuckets[0]>();
-    if (maxn <= kBuckets[1])
-        return batched_kernel<kBuckets[1]>();
-    if (maxn <= kBuckets[2])
-        return batched_kernel<kBuckets[2]>();
-    if (maxn <= kBuckets[3])
-        return batched_kernel<kBuckets[3]>();
-    return batched_kernel<kBuckets[4]>();
+    return {&k_batched<kBuckets[B]>...};
+}
+const auto kPersistent = persistent_table(std::make_integer_sequence<int, kNumBuckets>{});
+
+template <int K, int... B>
+constexpr std::array<WgKernel, sizeof...(B)> wg_table(std::integer_sequence<int, B...>)
+{
+    return {&k_batched_wg<kBuckets[B], K>...};
+}
+const std::array<std::array<WgKernel, kNumBuckets>, 4> kWg = {
+    wg_table<1>(std::make_integer_sequence<int, kNumBuckets>{}),
+    wg_table<2>(std::make_integer_sequence<int, kNumBuckets>{}),
+    wg_table<4>(std::make_integer_sequence<int, kNumBuckets>{}),
+    wg_table<8>(std::make_integer_sequence<int, kNumBuckets>{})};
+
+int log2_small(int k)
+{
+    return k == 1 ? 0 : k == 2 ? 1 : k == 4 ? 2 : k == 8 ? 3 : -1;
 }
 
 }  // namespace
 
 hipError_t boys_internal::launch_batched(const Desc *d_desc, const int2 *d_tiles, int32_t ntiles,
-                                         int32_t tile_args, uint32_t *d_counter, int maxn,
-                                         int grid, int block, hipStream_t s)
+                                         uint32_t *d_counter, int maxn, const Launch &L,
+                                         hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, d_counter);
-    if (ntiles > 0)
-        hipLaunchKernelGGL(pick_batched(maxn), dim3(grid), dim3(block), 0, s, d_desc, d_tiles,
-                           ntiles, tile_args, d_counter);
+    const int b = bucket_of(maxn);
+    if (L.schedule == 0) {
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, d_counter);
+        if (ntiles > 0)
+            hipLaunchKernelGGL(kPersistent[b], dim3(std::max(1, std::min(L.grid, ntiles))),
+                               dim3(L.block), 0, s, d_desc, d_tiles, ntiles, L.tile, d_counter);
+    } else {
+        const int k = log2_small(L.tile / L.block);
+        if (k < 0 || L.tile % L.block != 0)
+            return hipErrorInvalidValue;
+        if (ntiles > 0)
+            hipLaunchKernelGGL(kWg[k][b], dim3(ntiles), dim3(L.block), 0, s, d_desc, d_tiles,
+                               L.tile);
+    }
     return hipGetLastError();
 }
 
@@ -299,20 +374,21 @@ struct boys_plan {
     int32_t ntiles = 0;
     boys_tuning tuning{};
     int grid = 0;
-    BatchedKernel kernel = nullptr;
+    int maxn = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
 
 namespace {
 
-constexpr int kDefaultTile = 2048;
+constexpr int kDefaultTile = 256;
 constexpr int kDefaultBlock = 256;
 constexpr int kDefaultGridPerCU = 4;
+constexpr int kDefaultSchedule = 1;
 
 boys_tuning resolve(const boys_tuning *t)
 {
-    boys_tuning r{kDefaultTile, kDefaultBlock, kDefaultGridPerCU, 0};
+    boys_tuning r{kDefaultTile, kDefaultBlock, kDefaultGridPerCU, kDefaultSchedule};
     if (t) {
         if (t->tile > 0)
             r.tile = t->tile;
@@ -320,6 +396,7 @@ boys_tuning resolve(const boys_tuning *t)
             r.block = t->block;
         if (t->grid_per_cu > 0)
             r.grid_per_cu = t->grid_per_cu;
+        r.schedule = t->schedule;
     }
     return r;
 }
@@ -327,8 +404,18 @@ boys_tuning resolve(const boys_tuning *t)
 bool tuning_ok(const boys_tuning &t)
 {
     const bool block_ok = t.block == 64 || t.block == 128 || t.block == 256;
-    return block_ok && t.tile >= t.block && t.tile % t.block == 0 && t.tile <= (1 << 24) &&
-           t.grid_per_cu >= 1 && t.grid_per_cu <= 64;
+    if (!block_ok || t.tile < t.block || t.tile % t.block != 0 || t.tile > (1 << 24))
+        return false;
+    if (t.schedule == 0)
+        return t.grid_per_cu >= 1 && t.grid_per_cu <= 64;
+    if (t.schedule == 1)
+        return log2_small(t.tile / t.block) >= 0;
+    return false;
+}
+
+boys_internal::Launch launch_of(const boys_plan *p)
+{
+    return boys_internal::Launch{p->tuning.schedule, p->tuning.tile, p->tuning.block, p->grid};
 }
 
 double tile_cost(const boys_array &a, int64_t cnt)
@@ -387,7 +474,7 @@ boys_status build_schedule(boys_plan *p, const boys_array *arrays, int32_t count
     tiles.resize(all.size());
     for (size_t i = 0; i < all.size(); ++i)
         tiles[i] = make_int2(all[i].array, all[i].slice);
-    p->kernel = pick_batched(maxn);
+    p->maxn = maxn;
     p->ntiles = (int32_t)all.size();
     return BOYS_OK;
 }
@@ -402,11 +489,8 @@ boys_status capture_graph(boys_plan *p)
         (void)hipStreamDestroy(s);
         return BOYS_ERR_DEVICE;
     }
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, p->d_counter);
-    if (p->ntiles > 0)
-        hipLaunchKernelGGL(p->kernel, dim3(p->grid), dim3(p->tuning.block), 0, s, p->d_desc,
-                           p->d_tiles, p->ntiles, p->tuning.tile, p->d_counter);
-    if (hipGetLastError() != hipSuccess)
+    if (boys_internal::launch_batched(p->d_desc, p->d_tiles, p->ntiles, p->d_counter, p->maxn,
+                                      launch_of(p), s) != hipSuccess)
         st = BOYS_ERR_DEVICE;
     if (hipStreamEndCapture(s, &p->graph) != hipSuccess)
         st = BOYS_ERR_DEVICE;

@@ -37,6 +37,7 @@ struct HipExec {
     int max_batch = 256;
     int grid = 1024;
     int block = 256;
+    int schedule = 1;  // one workgroup per tile (tile = block x 1, 2, 4 or 8)
     char *pool_base = nullptr;
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
@@ -102,10 +103,9 @@ struct HipExec {
                                   st) == hipSuccess;
         ok = ok && hipMemcpyAsync(d_tiles[s], h_tiles[s], sizeof(int2) * ts.size(),
                                   hipMemcpyHostToDevice, st) == hipSuccess;
+        const boys_internal::Launch L{schedule, (int)tile, block, grid};
         ok = ok && boys_internal::launch_batched(d_desc[s], d_tiles[s], (int32_t)ts.size(),
-                                                 (int32_t)tile, d_counter[s], maxn,
-                                                 std::min<int>(grid, (int)ts.size()), block,
-                                                 st) == hipSuccess;
+                                                 d_counter[s], maxn, L, st) == hipSuccess;
         ok = ok && hipEventRecord(events[s], st) == hipSuccess;
         if (!ok)
             errors++;
@@ -185,10 +185,10 @@ boys_status boys_server_create(boys_server **out, const boys_server_config *cfg)
     *out = nullptr;
     const int streams = cfg->streams > 0 ? cfg->streams : 4;
     const int max_batch = cfg->max_batch > 0 ? cfg->max_batch : 256;
-    const int tile = cfg->tile > 0 ? cfg->tile : 2048;
+    const int tile = cfg->tile > 0 ? cfg->tile : 256;
     const int max_tiles = cfg->max_tiles > 0 ? cfg->max_tiles : 65536;
-    if (cfg->budget_bytes <= 0 || streams > 32 || max_batch > 65536 || tile % 256 != 0 ||
-        max_tiles > (1 << 24))
+    if (cfg->budget_bytes <= 0 || streams > 32 || max_batch > 65536 ||
+        !(tile == 256 || tile == 512 || tile == 1024 || tile == 2048) || max_tiles > (1 << 24))
         return BOYS_ERR_INVALID_ARGUMENT;
     boys_server *s = new (std::nothrow) boys_server();
     if (!s)

@@ -29,7 +29,7 @@ def _pc(p):
 
 class Server:
     def __init__(self, budget_bytes: int = 8 << 30, streams: int = 4, max_batch: int = 256,
-                 tile: int = 2048, max_tiles: int = 65536, device=None):
+                 tile: int = 256, max_tiles: int = 65536, device=None):
         import torch
         self.device = torch.device("cuda") if device is None else torch.device(device)
         cfg = BoysServerConfig(int(budget_bytes), streams, max_batch, tile, max_tiles)

@@ -101,13 +101,38 @@ def test_full_batched_workload_equals_solo():
     plan.close()
 
 
-def test_autotune_picks_a_candidate():
+@pytest.mark.parametrize("tuning", [
+    {"schedule": 0, "tile": 2048, "block": 256, "grid_per_cu": 4},
+    {"schedule": 0, "tile": 256, "block": 64, "grid_per_cu": 16},
+    {"schedule": 1, "tile": 256, "block": 256, "grid_per_cu": 1},
+    {"schedule": 1, "tile": 1024, "block": 128, "grid_per_cu": 1},
+    {"schedule": 1, "tile": 512, "block": 64, "grid_per_cu": 1}])
+def test_every_schedule_equals_solo(tuning):
     torch = require_gpu()
     import paper_2504_07637_amd as boys
+    xs, hs, nm, pr = _batch(torch, 300, 70, nmax_hi=36)
+    _say(f"[schedule] {tuning}")
+    plan = boys.Plan(xs, nm, pr, tuning=tuning)
+    plan.execute()
+    solo = _solo(boys, xs, nm, pr)
+    torch.cuda.synchronize()
+    for k, (o, s) in enumerate(zip(plan.outs, solo)):
+        assert same_bits(o.cpu().numpy(), s.cpu().numpy()).all(), (tuning, k)
+    plan.close()
+
+
+def test_autotune_picks_a_candidate(tmp_path, monkeypatch):
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    from paper_2504_07637_amd import tuning
     xs, hs, nm, pr = _batch(torch, 200, 60)
-    cands = [{"tile": 1024, "block": 256, "grid_per_cu": 2},
-             {"tile": 2048, "block": 256, "grid_per_cu": 4},
-             {"tile": 512, "block": 128, "grid_per_cu": 8}]
+    cands = [{"schedule": 0, "tile": 1024, "block": 256, "grid_per_cu": 2},
+             {"schedule": 0, "tile": 2048, "block": 256, "grid_per_cu": 4},
+             {"schedule": 1, "tile": 512, "block": 128, "grid_per_cu": 1}]
     best, times = boys.autotune(xs, nm, pr, cands, warmup=1, reps=2)
     assert best in cands and all(t > 0 for t in times)
     assert times[cands.index(best)] == min(times)
+    monkeypatch.setenv("BOYS_TUNING_FILE", str(tmp_path / "tuning.json"))
+    t1, info1 = tuning.tuned(xs, nm, pr, candidates=cands, warmup=1, reps=2)
+    t2, info2 = tuning.tuned(xs, nm, pr, candidates=cands)
+    assert not info1["cached"] and info2["cached"] and t1 == t2 and t1 in cands
