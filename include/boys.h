@@ -22,8 +22,10 @@
  *   - x is binary64, contiguous, n elements.
  *   - out holds (n_max + 1) rows of ld_out elements: F_m(x[i]) is at out[m * ld_out + i]
  *     (structure of arrays), binary64 for BOYS_FP64 and binary32 for BOYS_FP32.
- *     Requires ld_out >= n.  Alignment: 8 bytes (FP64) or 4 bytes (FP32); 256 bytes
- *     gives the best store coalescing.
+ *     Requires ld_out >= n.  Alignment: 8 bytes (FP64) or 4 bytes (FP32).  Rows that
+ *     start on 128-byte boundaries (out 128-byte aligned and ld_out a multiple of 16
+ *     binary64 / 32 binary32 elements) are written as whole cache lines; other strides
+ *     work but cost up to a third of the store bandwidth.
  *   - stream is a hipStream_t (NULL = the null stream).  Calls only enqueue work and
  *     return; results are ready when the stream reaches them.
  *   - Inputs outside x >= 0: x < 0 or NaN gives NaN for every m; x = +inf gives 0.
@@ -82,8 +84,8 @@ typedef struct {
 /*
  * Launch parameters of a batched launch (0 in tile/block/grid_per_cu = library default).
  * schedule 0: persistent workgroups (grid_per_cu per compute unit) take tiles from a work
- *             counter in longest-first order;
- * schedule 1: one workgroup per tile, dispatched by the hardware in longest-first order;
+ *             counter in table order;
+ * schedule 1: one workgroup per tile, dispatched by the hardware in table order;
  *             tile must be block x 1, 2, 4 or 8.
  */
 typedef struct {
@@ -91,6 +93,9 @@ typedef struct {
     int32_t block;       /* threads per workgroup: 64, 128 or 256 */
     int32_t grid_per_cu; /* schedule 0: persistent workgroups per compute unit (1..64) */
     int32_t schedule;    /* 0 or 1 (above) */
+    int32_t order;       /* tile order: 0 longest first; 1 array by array (each array's
+                            tiles consecutive); 2 grouped by (precision, n_max), then
+                            array by array */
 } boys_tuning;
 
 /*
@@ -102,7 +107,7 @@ typedef struct {
 boys_status boys_eval_batched(const boys_array *arrays, int32_t count, void *stream);
 
 /*
- * Plans: a schedule (tiles ordered by decreasing cost, descriptor and tile tables in
+ * Plans: a schedule (tiles in the tuning's order, descriptor and tile tables in
  * device memory, a work counter) and a HIP graph of the batched launch (schedule 0:
  * [reset counter, persistent kernel]; schedule 1: [one workgroup per tile]) built once
  * for a batch and replayed by boys_plan_execute.  tuning may be NULL for the
@@ -132,7 +137,7 @@ boys_status boys_autotune(const boys_array *arrays, int32_t count, const boys_tu
  * thread.  Each request is one argument array (host memory; pinned memory gives truly
  * asynchronous copies), evaluated as by boys_eval into device memory owned by the server:
  *   - requests are admitted in arrival order while their footprint (n*8 bytes for x plus
- *     (n_max+1)*n*{8,4} bytes of output, each rounded up to 256 bytes) fits the budget;
+ *     (n_max+1)*ld*{8,4} bytes of output, each rounded up to 256 bytes) fits the budget;
  *     one that does not fit waits until releases free enough memory;
  *   - admitted requests are launched at the next opportunity: whenever one of the
  *     `streams` execution slots is free, every admitted request not yet launched (up to
@@ -140,7 +145,8 @@ boys_status boys_autotune(const boys_array *arrays, int32_t count, const boys_tu
  *     launch on that slot's stream; batches on different slots overlap
  *     (continuous batching);
  *   - a request completes when its batch's event completes; its output stays in device
- *     memory (rows of ld = n elements) until boys_server_release.
+ *     memory until boys_server_release (rows of ld elements, ld = n rounded up to a
+ *     multiple of 16 binary64 / 32 binary32 elements).
  * Times are seconds on the server's monotonic clock.  x_host must stay valid and
  * unchanged until the request completes.  All functions are thread-safe.
  */

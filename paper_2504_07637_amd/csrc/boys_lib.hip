@@ -385,10 +385,11 @@ constexpr int kDefaultTile = 256;
 constexpr int kDefaultBlock = 256;
 constexpr int kDefaultGridPerCU = 4;
 constexpr int kDefaultSchedule = 1;
+constexpr int kDefaultOrder = 1;
 
 boys_tuning resolve(const boys_tuning *t)
 {
-    boys_tuning r{kDefaultTile, kDefaultBlock, kDefaultGridPerCU, kDefaultSchedule};
+    boys_tuning r{kDefaultTile, kDefaultBlock, kDefaultGridPerCU, kDefaultSchedule, kDefaultOrder};
     if (t) {
         if (t->tile > 0)
             r.tile = t->tile;
@@ -397,6 +398,7 @@ boys_tuning resolve(const boys_tuning *t)
         if (t->grid_per_cu > 0)
             r.grid_per_cu = t->grid_per_cu;
         r.schedule = t->schedule;
+        r.order = t->order;
     }
     return r;
 }
@@ -405,6 +407,8 @@ bool tuning_ok(const boys_tuning &t)
 {
     const bool block_ok = t.block == 64 || t.block == 128 || t.block == 256;
     if (!block_ok || t.tile < t.block || t.tile % t.block != 0 || t.tile > (1 << 24))
+        return false;
+    if (t.order < 0 || t.order > 2)
         return false;
     if (t.schedule == 0)
         return t.grid_per_cu >= 1 && t.grid_per_cu <= 64;
@@ -468,9 +472,24 @@ boys_status build_schedule(boys_plan *p, const boys_array *arrays, int32_t count
         if (A.n > 0)
             maxn = std::max(maxn, A.n_max);
     }
-    // longest processing time first; ties keep array order, so the tiles of one
-    // (precision, n_max) class run together and share the instruction cache
-    std::stable_sort(all.begin(), all.end(), [](const T &l, const T &r) { return l.cost > r.cost; });
+    if (p->tuning.order == 0) {
+        // longest processing time first (ties keep array order)
+        std::stable_sort(all.begin(), all.end(),
+                         [](const T &l, const T &r) { return l.cost > r.cost; });
+    } else if (p->tuning.order == 2) {
+        // by (precision, n_max) class, heavier classes first, then array by array
+        std::stable_sort(all.begin(), all.end(), [arrays](const T &l, const T &r) {
+            const boys_array &A = arrays[l.array], &B = arrays[r.array];
+            const double ca = tile_cost(A, 1), cb = tile_cost(B, 1);
+            if (ca != cb)
+                return ca > cb;
+            if (A.precision != B.precision)
+                return A.precision < B.precision;
+            return A.n_max > B.n_max;
+        });
+    }
+    // order 1: as built, array by array with each array's tiles consecutive, so the
+    // workgroups running at one time write neighbouring pieces of the same output rows
     tiles.resize(all.size());
     for (size_t i = 0; i < all.size(); ++i)
         tiles[i] = make_int2(all[i].array, all[i].slice);

@@ -2,7 +2,8 @@
 //
 // A scheduler thread drives serve_core.h's Core with a HIP executor:
 //   * one device allocation of the budget is the pool; an admitted request owns a
-//     contiguous piece of it: its x copy, then its (n_max+1) x n output rows (ld = n);
+//     contiguous piece of it: its x copy, then its (n_max+1) output rows, each starting
+//     on a 128-byte boundary (ld = n rounded up to 16 binary64 / 32 binary32 elements);
 //   * K execution slots, each a HIP stream with its own pinned staging and device
 //     buffers for the descriptor and tile tables and its own work counter;
 //   * a launch on a slot enqueues, in stream order, the host-to-device copies of the
@@ -77,7 +78,7 @@ struct HipExec {
         for (int a = 0; a < nb; ++a) {
             const Request &r = *batch[a];
             char *base = pool_base + r.off;
-            h_desc[s][a] = Desc{reinterpret_cast<const double *>(base), base + r.x_bytes, r.n, r.n,
+            h_desc[s][a] = Desc{reinterpret_cast<const double *>(base), base + r.x_bytes, r.n, r.ld,
                                 r.n_max, r.prec};
             maxn = std::max(maxn, r.n_max);
             const int64_t nt = (r.n + tile - 1) / tile;
@@ -293,7 +294,7 @@ boys_status boys_server_result(boys_server *s, uint64_t id, const void **out, in
     if (out)
         *out = s->ex.pool_base + r->off + r->x_bytes;
     if (ld)
-        *ld = r->n;
+        *ld = r->ld;
     if (t_submit)
         *t_submit = r->t_submit;
     if (t_done)
@@ -316,7 +317,7 @@ boys_status boys_server_copy_result(boys_server *s, uint64_t id, void *dst, int6
         const size_t es = r->prec == BOYS_FP64 ? 8 : 4;
         src = s->ex.pool_base + r->off + r->x_bytes;
         width = (size_t)r->n * es;
-        spitch = width;
+        spitch = (size_t)r->ld * es;
         rows = (size_t)r->n_max + 1;
         const size_t dpitch = (size_t)ld_dst * es;
         if (hipMemcpy2DAsync(dst, dpitch, src, spitch, width, rows, hipMemcpyDeviceToDevice,

@@ -114,15 +114,23 @@ struct Request {
     const double *x_host = nullptr;
     uint64_t off = 0;      // pool offset: x at off, output at off + x_bytes
     uint64_t x_bytes = 0;  // aligned size of the x copy
+    int64_t ld = 0;        // output row stride (elements)
     uint64_t bytes = 0;    // whole footprint
     int slot = -1;
     State state = State::Queued;
     double t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
 };
 
+// row stride of a request's output: every row starts on a 128-byte boundary
+inline int64_t padded_ld(int64_t n, int32_t prec)
+{
+    const int64_t q = prec == 0 ? 16 : 32;
+    return (n + q - 1) / q * q;
+}
+
 inline uint64_t out_bytes(int64_t n, int32_t n_max, int32_t prec)
 {
-    return (uint64_t)(n_max + 1) * (uint64_t)n * (prec == 0 ? 8u : 4u);
+    return (uint64_t)(n_max + 1) * (uint64_t)padded_ld(n, prec) * (prec == 0 ? 8u : 4u);
 }
 
 inline uint64_t footprint(int64_t n, int32_t n_max, int32_t prec)
@@ -168,6 +176,7 @@ class Core {
         r.x_host = x_host;
         r.bytes = fp;
         r.x_bytes = align_up((uint64_t)n * 8u);
+        r.ld = padded_ld(n, prec);
         r.t_submit = now;
         reqs_[r.id] = r;
         queue_.push_back(r.id);

@@ -8,8 +8,9 @@ device, library build and a coarse signature of the batch, and keeps it in a JSO
 Tunable choices (the per-argument work is one sequential chain, so a lane always owns
 whole arguments): the schedule (persistent workgroups with a work counter, or one
 workgroup per tile), the workgroup size, the arguments per lane (tile = block x 1, 2, 4
-or 8 for one workgroup per tile) and, for the persistent schedule, the tile size and the
-number of workgroups per compute unit.
+or 8 for one workgroup per tile), the tile order (longest first, array by array, or
+grouped by class) and, for the persistent schedule, the tile size and the number of
+workgroups per compute unit.
 """
 from __future__ import annotations
 
@@ -21,10 +22,10 @@ import os
 from . import _lib
 
 CANDIDATES = (
-    [{"schedule": 1, "block": b, "tile": b * k, "grid_per_cu": 1}
-     for b in (128, 256) for k in (1, 2, 4)]
-    + [{"schedule": 0, "block": 256, "tile": t, "grid_per_cu": g}
-       for t in (1024, 2048, 4096) for g in (2, 4, 8)]
+    [{"schedule": 1, "block": b, "tile": b * k, "grid_per_cu": 1, "order": o}
+     for o in (1, 2, 0) for b in (128, 256) for k in (1, 2, 4)]
+    + [{"schedule": 0, "block": 256, "tile": t, "grid_per_cu": g, "order": o}
+       for o in (1, 0) for t in (1024, 4096) for g in (2, 4)]
 )
 
 

@@ -57,7 +57,7 @@ def test_argument_errors_are_reported_before_any_launch():
     arr[0].x, arr[0].out, arr[0].n, arr[0].ld_out, arr[0].n_max, arr[0].precision = (
         None, None, 5, 5, 2, L.FP64)
     assert lib.boys_plan_create(ctypes.byref(p), arr, 1, None) == L.ERR_INVALID_ARGUMENT
-    bad = L.BoysTuning(100, 256, 4, 0)  # tile not a multiple of the block
+    bad = L.BoysTuning(100, 256, 4, 0, 1)  # tile not a multiple of the block
     arr[0].n = 0
     assert lib.boys_plan_create(ctypes.byref(p), arr, 1, ctypes.byref(bad)) == L.ERR_INVALID_ARGUMENT
     assert lib.boys_plan_execute(None, None) == L.ERR_INVALID_ARGUMENT

@@ -36,7 +36,9 @@ def harness(tmp_path_factory):
 
 def footprint(n, nmax, prec):
     a = lambda v: (v + 255) // 256 * 256
-    return a(8 * n) + a((nmax + 1) * n * (8 if prec == 0 else 4))
+    q = 16 if prec == 0 else 32
+    ld = (n + q - 1) // q * q
+    return a(8 * n) + a((nmax + 1) * ld * (8 if prec == 0 else 4))
 
 
 def simulate(L, t, ln, nm, pr, budget, slots=4, max_batch=256, bw=1e12, dt=2e-6):
