@@ -19,10 +19,10 @@
 // that follows the same steps):
 //   * every +, -, *, / and sqrt is a single correctly rounded IEEE operation; nothing is
 //     contracted into an fma except where an fma is written out;
-//   * exp(-x) is the correctly rounded binary64 value, computed in double-double
-//     (Tang's table method: a = k ln2/256 + r, 2^(j/256) from a table, a degree-8
-//     Taylor polynomial of exp(r)); the error before the last rounding is below 2^-95
-//     relative, so a misrounding needs exp(-x) within 2^-95 of a rounding boundary;
+//   * exp(-x) is the correctly rounded binary64 value (Tang's table method with a
+//     double-only fast path and Ziv's rounding test; when the test cannot decide, a
+//     double-double evaluation with error below 2^-95 before its one rounding, so a
+//     misrounding needs exp(-x) within 2^-95 of a rounding boundary);
 //   * y^n is left-to-right binary powering, y^(n+1/2) = y^n * sqrt(y);
 //   * the recursion F_{m-1} = RN(RN(RN(2x) F_m) + e) / (2m-1)) divides by the odd
 //     constant d = 2m-1 as q = t*r, r = RN(1/d),
@@ -92,20 +92,21 @@ __host__ __device__ __forceinline__ dd add_dd_fast(dd a, dd b)
 // ---------------------------------------------------------------------------------
 // correctly rounded exp(a) for a in [-120, 0]
 //
-// tab: the 256 pairs (hi, lo) of 2^(j/256) (kept in LDS by the kernels).
+// tab: the 256 pairs (hi, lo) of 2^(j/256) (kept in L1 or LDS by the kernels).
+// a = k ln2/256 + r with |r| <= ln2/512 and r a double-double (k * L1 exact), then
+// exp(a) = 2^m 2^(j/256) exp(r), k = 256 m + j.
+//
+// Fast path (Ziv's strategy): exp(r) - 1 = r_hi + w with w = r_lo + r_hi r_lo +
+// r_hi^2 P(r_hi), P the Taylor polynomial 1/2 + r/6 + .. + r^4/720 (truncation below
+// 2^-78); the result S + e = T (1 + r_hi + w) as an unevaluated sum has a relative
+// error below 2^-70.  If S + 1.0000152 e still rounds to S (|e| stays 2^-16 of a
+// half-ulp away from a rounding boundary, more than the error can cover) then S is the
+// correctly rounded value.  Otherwise, about once in 2^16 arguments, the slow path
+// recomputes exp(r) in double-double (error below 2^-95) and rounds once.
 
-__host__ __device__ __forceinline__ double exp_rn(double a, const double2 *__restrict__ tab)
+__host__ __device__ __forceinline__ double exp_rn_slow(dd r, double2 T, int m)
 {
     using namespace boys_tab;
-    const double kd = __builtin_rint(a * kInvLn2x256);
-    const int k = (int)kd;
-    const int j = k & 255;
-    const int m = (k - j) / 256;
-    // r = a - k ln2/256 as a double-double; k * L1 is exact (L1 has 36 bits, |k| < 2^17)
-    const double t = __builtin_fma(-kd, kLn2d256_1, a);
-    const dd p2 = two_prod(kd, kLn2d256_2);
-    dd r = two_sum(t, -p2.hi);
-    r = fast_two_sum(r.hi, (r.lo - p2.lo) - kd * kLn2d256_3);
     const double rh = r.hi;
     // exp(r) - 1 = r + r^2 s2, s2 = 1/2 + r s3, s3 = 1/6 + r s4, s4 = 1/24 + r s5
     const double s5 = kInvFact5_hi + rh * (kInvFact6_hi + rh * (kInvFact7_hi + rh * kInvFact8_hi));
@@ -114,8 +115,6 @@ __host__ __device__ __forceinline__ double exp_rn(double a, const double2 *__res
     const dd s3 = add_dd_fast(dd{kInvFact3_hi, kInvFact3_lo}, mul_dd(r, s4));
     const dd s2 = add_dd_fast(dd{0.5, 0.0}, mul_dd(r, s3));
     const dd pm1 = add_dd_fast(r, mul_dd(r, mul_dd(r, s2)));
-    // 2^(j/256) (1 + p)
-    const double2 T = tab[j];
     dd q = two_prod(T.x, pm1.hi);
     double lo = __builtin_fma(T.x, pm1.lo, q.lo);
     lo = __builtin_fma(T.y, pm1.hi, lo);
@@ -123,6 +122,34 @@ __host__ __device__ __forceinline__ double exp_rn(double a, const double2 *__res
     const dd s = fast_two_sum(T.x, q.hi);
     const double v = s.hi + (s.lo + lo);
     return __builtin_ldexp(v, m);
+}
+
+__host__ __device__ __forceinline__ double exp_rn(double a, const double2 *__restrict__ tab)
+{
+    using namespace boys_tab;
+    const double kd = __builtin_rint(a * kInvLn2x256);
+    const int k = (int)kd;
+    const int j = k & 255;
+    const int m = (k - j) / 256;
+    const double t = __builtin_fma(-kd, kLn2d256_1, a);
+    const dd p2 = two_prod(kd, kLn2d256_2);
+    dd r = two_sum(t, -p2.hi);
+    r = fast_two_sum(r.hi, (r.lo - p2.lo) - kd * kLn2d256_3);
+    const double2 T = tab[j];
+    const double rh = r.hi;
+    double P = __builtin_fma(rh, kInvFact6_hi, kInvFact5_hi);
+    P = __builtin_fma(rh, P, kInvFact4_hi);
+    P = __builtin_fma(rh, P, kInvFact3_hi);
+    P = __builtin_fma(rh, P, 0.5);
+    const double w = __builtin_fma(rh * rh, P, __builtin_fma(rh, r.lo, r.lo));
+    const dd q = two_prod(T.x, rh);
+    double lo = __builtin_fma(T.x, w, q.lo);
+    lo = __builtin_fma(T.y, rh, lo) + T.y;
+    const dd s = fast_two_sum(T.x, q.hi);
+    const double e = s.lo + lo;
+    if (s.hi + e * 0x1.0001p+0 == s.hi)
+        return __builtin_ldexp(s.hi, m);
+    return exp_rn_slow(r, T, m);
 }
 
 // ---------------------------------------------------------------------------------
