@@ -7,7 +7,7 @@
 //                    non-temporal accesses (for a wave, 512 contiguous bytes per binary64
 //                    row).  The binary64 class reads the 4 KiB exp table through the L1
 //                    cache with 128-thread workgroups; the mixed class stages it in LDS
-//                    with 256-thread workgroups (the faster shape for each, by measurement).
+//                    with 512-thread workgroups (the faster shape for each, by measurement).
 //   k_batched<MAXN>  persistent workgroups pull tiles from a device counter; a tile is
 //                    one slice of one array, so (precision, n_max) is uniform per tile and
 //                    the per-tile dispatch is a scalar branch to the same unrolled bodies
@@ -75,7 +75,7 @@ __device__ __forceinline__ void body_f32(const double *__restrict__ x, float *__
 template <int C>
 constexpr int plain_block()
 {
-    return C == BOYS_FP64 ? 128 : 256;
+    return C == BOYS_FP64 ? 128 : 512;
 }
 
 template <int C, int N>
