@@ -21,7 +21,8 @@
  *     given until updated or destroyed).
  *   - x is binary64, contiguous, n elements.
  *   - out holds (n_max + 1) rows of ld_out elements: F_m(x[i]) is at out[m * ld_out + i]
- *     (structure of arrays), binary64 for BOYS_FP64 and binary32 for BOYS_FP32.
+ *     (structure of arrays), binary64 for BOYS_FP64 / BOYS_FP64_PLUS and binary32 for
+ *     BOYS_FP32.
  *     Requires ld_out >= n.  Alignment: 8 bytes (FP64) or 4 bytes (FP32).  Rows that
  *     start on 128-byte boundaries (out 128-byte aligned and ld_out a multiple of 16
  *     binary64 / 32 binary32 elements) are written as whole cache lines; other strides
@@ -50,7 +51,12 @@ typedef enum {
     /* mixed class: u/v, Q~ and the power Q~^(n+1/2) and the recursion in binary32,
        x + W and c_n / G^(n+1/2) in binary64 (the power whose rounding error is
        amplified by n+1/2); output binary32 */
-    BOYS_FP32 = 1
+    BOYS_FP32 = 1,
+    /* binary64 with the option of section "Computations" for a few more bits in F_n:
+       the order n_max+1 approximant (and its cut-off z_{n_max+1,53}) gives F_{n_max+1},
+       one more step of Eq. r gives F_{n_max}, which is not stored; output binary64
+       (F_{n_max} gains about 3 bits at n_max >= 16); n_max <= boys_max_nmax - 1 */
+    BOYS_FP64_PLUS = 2
 } boys_precision;
 
 typedef enum {

@@ -13,10 +13,10 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import FP32, FP64, BoysArray, BoysError, BoysTuning
+from ._lib import FP32, FP64, FP64_PLUS, BoysArray, BoysError, BoysTuning
 
 __all__ = ["boys_eval", "boys_eval_batched", "Plan", "autotune", "max_nmax", "cutoff",
-           "precision_code", "padded_ld", "empty_out", "BoysError", "FP64", "FP32"]
+           "precision_code", "padded_ld", "empty_out", "BoysError", "FP64", "FP32", "FP64_PLUS"]
 
 
 def precision_code(precision) -> int:
@@ -24,6 +24,8 @@ def precision_code(precision) -> int:
         return FP64
     if precision in (FP32, "fp32", "float32", "mixed"):
         return FP32
+    if precision in (FP64_PLUS, "fp64plus", "fp64+"):
+        return FP64_PLUS
     raise ValueError(f"unknown precision {precision!r}")
 
 
@@ -34,7 +36,7 @@ def _torch():
 
 def _out_dtype(code):
     torch = _torch()
-    return torch.float64 if code == FP64 else torch.float32
+    return torch.float32 if code == FP32 else torch.float64
 
 
 def _stream_ptr(stream, device):
@@ -49,7 +51,7 @@ def padded_ld(n: int, precision) -> int:
 
     Rows that straddle cache lines are written as partial lines, which costs up to a
     third of the store bandwidth (measured); outputs allocated here use this stride."""
-    q = 16 if precision_code(precision) == FP64 else 32
+    q = 32 if precision_code(precision) == FP32 else 16
     return max(q, (n + q - 1) // q * q)
 
 

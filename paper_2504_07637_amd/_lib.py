@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(PKG, "libboys.so")
 
 FP64 = 0
 FP32 = 1
+FP64_PLUS = 2
 
 OK = 0
 ERR_INVALID_ARGUMENT = 1

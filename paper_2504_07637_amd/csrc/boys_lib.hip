@@ -42,6 +42,8 @@ constexpr int kMaxN = kMaxN64 > kMaxN32 ? kMaxN64 : kMaxN32;
 // ---------------------------------------------------------------------------------
 // device code
 
+using boys_internal::Desc;
+
 __device__ __forceinline__ void load_exp_table(double2 *tab)
 {
     for (int t = threadIdx.x; t < 256; t += blockDim.x)
@@ -60,6 +62,23 @@ __device__ __forceinline__ void body_f64(const double *__restrict__ x, double *_
         __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
 }
 
+// binary64, F_0..F_N from the order N+1 approximant and one more recursion step
+template <int N>
+__device__ __forceinline__ void body_f64plus(const double *__restrict__ x,
+                                             double *__restrict__ out, int64_t ld, int64_t i,
+                                             const double2 *tab)
+{
+    double F[N + 2];
+    boys::eval_f64<N + 1>(__builtin_nontemporal_load(x + i), tab, F);
+#pragma unroll
+    for (int m = 0; m <= N; ++m)
+        __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
+}
+
+// one argument of class C (BOYS_FP64, BOYS_FP32 or BOYS_FP64_PLUS) at order N
+template <int C, int N>
+__device__ __forceinline__ void body(const Desc &d, int64_t i, const double2 *tab);
+
 template <int N>
 __device__ __forceinline__ void body_f32(const double *__restrict__ x, float *__restrict__ out,
                                          int64_t ld, int64_t i, const double2 *tab)
@@ -71,11 +90,34 @@ __device__ __forceinline__ void body_f32(const double *__restrict__ x, float *__
         __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
 }
 
+constexpr int cmin(int a, int b)
+{
+    return a < b ? a : b;
+}
+
 // block size of the plain kernel per class
 template <int C>
 constexpr int plain_block()
 {
-    return C == BOYS_FP64 ? 128 : 512;
+    return C == BOYS_FP32 ? 512 : 128;
+}
+
+// largest order of a class
+template <int C>
+constexpr int class_max()
+{
+    return C == BOYS_FP32 ? kMaxN32 : C == BOYS_FP64 ? kMaxN64 : kMaxN64 - 1;
+}
+
+template <int C, int N>
+__device__ __forceinline__ void body(const Desc &d, int64_t i, const double2 *tab)
+{
+    if constexpr (C == BOYS_FP64)
+        body_f64<N>(d.x, static_cast<double *>(d.out), d.ld, i, tab);
+    else if constexpr (C == BOYS_FP64_PLUS)
+        body_f64plus<N>(d.x, static_cast<double *>(d.out), d.ld, i, tab);
+    else
+        body_f32<N>(d.x, static_cast<float *>(d.out), d.ld, i, tab);
 }
 
 template <int C, int N>
@@ -84,7 +126,7 @@ __global__ __launch_bounds__(plain_block<C>()) void k_plain(const double *__rest
 {
     constexpr int BS = plain_block<C>();
     const double2 *tab;
-    if constexpr (C == BOYS_FP64) {
+    if constexpr (C != BOYS_FP32) {
         tab = reinterpret_cast<const double2 *>(boys_tab::kExp2Tab);
     } else {
         __shared__ double2 lds_tab[256];
@@ -97,23 +139,19 @@ __global__ __launch_bounds__(plain_block<C>()) void k_plain(const double *__rest
     if (i < n) {
         if constexpr (C == BOYS_FP64)
             body_f64<N>(x, static_cast<double *>(out), ld, i, tab);
+        else if constexpr (C == BOYS_FP64_PLUS)
+            body_f64plus<N>(x, static_cast<double *>(out), ld, i, tab);
         else
             body_f32<N>(x, static_cast<float *>(out), ld, i, tab);
     }
 }
 
-using boys_internal::Desc;
-
 template <int C, int N>
 __device__ __forceinline__ void tile_body(const Desc &d, int64_t start, int64_t cnt,
                                           const double2 *tab)
 {
-    for (int64_t j = threadIdx.x; j < cnt; j += blockDim.x) {
-        if constexpr (C == BOYS_FP64)
-            body_f64<N>(d.x, static_cast<double *>(d.out), d.ld, start + j, tab);
-        else
-            body_f32<N>(d.x, static_cast<float *>(d.out), d.ld, start + j, tab);
-    }
+    for (int64_t j = threadIdx.x; j < cnt; j += blockDim.x)
+        body<C, N>(d, start + j, tab);
 }
 
 // scalar dispatch over n (wave-uniform) to the unrolled bodies N = 0..MAXN
@@ -152,10 +190,14 @@ __global__ __launch_bounds__(256) void k_batched(const Desc *__restrict__ descs,
         const int64_t rem = d.n - start;
         const int64_t cnt = rem < tile_args ? rem : tile_args;
         const int n = __builtin_amdgcn_readfirstlane(d.n_max);
-        if (__builtin_amdgcn_readfirstlane(d.prec) == BOYS_FP64)
-            dispatch_n<BOYS_FP64, (MAXN < kMaxN64 ? MAXN : kMaxN64)>(n, d, start, cnt, tab);
+        const int prec = __builtin_amdgcn_readfirstlane(d.prec);
+        if (prec == BOYS_FP64)
+            dispatch_n<BOYS_FP64, cmin(MAXN, class_max<BOYS_FP64>())>(n, d, start, cnt, tab);
+        else if (prec == BOYS_FP32)
+            dispatch_n<BOYS_FP32, cmin(MAXN, class_max<BOYS_FP32>())>(n, d, start, cnt, tab);
         else
-            dispatch_n<BOYS_FP32, (MAXN < kMaxN32 ? MAXN : kMaxN32)>(n, d, start, cnt, tab);
+            dispatch_n<BOYS_FP64_PLUS, cmin(MAXN, class_max<BOYS_FP64_PLUS>())>(n, d, start, cnt,
+                                                                                 tab);
     }
 }
 
@@ -167,12 +209,8 @@ __device__ __forceinline__ void tile_body_unrolled(const Desc &d, int64_t start,
 #pragma unroll
     for (int a = 0; a < K; ++a) {
         const int64_t i = start + (int64_t)a * blockDim.x + threadIdx.x;
-        if (i < d.n) {
-            if constexpr (C == BOYS_FP64)
-                body_f64<N>(d.x, static_cast<double *>(d.out), d.ld, i, tab);
-            else
-                body_f32<N>(d.x, static_cast<float *>(d.out), d.ld, i, tab);
-        }
+        if (i < d.n)
+            body<C, N>(d, i, tab);
     }
 }
 
@@ -201,12 +239,15 @@ __global__ __launch_bounds__(256) void k_batched_wg(const Desc *__restrict__ des
     const Desc d = descs[a];
     const int64_t start = (int64_t)__builtin_amdgcn_readfirstlane(ts.y) * tile_args;
     const int n = __builtin_amdgcn_readfirstlane(d.n_max);
-    if (__builtin_amdgcn_readfirstlane(d.prec) == BOYS_FP64) {
-        dispatch_wg<BOYS_FP64, (MAXN < kMaxN64 ? MAXN : kMaxN64), K>(
-            n, d, start, reinterpret_cast<const double2 *>(boys_tab::kExp2Tab));
-    } else {
+    const int prec = __builtin_amdgcn_readfirstlane(d.prec);
+    const double2 *gtab = reinterpret_cast<const double2 *>(boys_tab::kExp2Tab);
+    if (prec == BOYS_FP64) {
+        dispatch_wg<BOYS_FP64, cmin(MAXN, class_max<BOYS_FP64>()), K>(n, d, start, gtab);
+    } else if (prec == BOYS_FP32) {
         load_exp_table(lds_tab);
-        dispatch_wg<BOYS_FP32, (MAXN < kMaxN32 ? MAXN : kMaxN32), K>(n, d, start, lds_tab);
+        dispatch_wg<BOYS_FP32, cmin(MAXN, class_max<BOYS_FP32>()), K>(n, d, start, lds_tab);
+    } else {
+        dispatch_wg<BOYS_FP64_PLUS, cmin(MAXN, class_max<BOYS_FP64_PLUS>()), K>(n, d, start, gtab);
     }
 }
 
@@ -244,7 +285,7 @@ hipError_t launch_plain(const double *x, int64_t n, void *out, int64_t ld, hipSt
 {
     constexpr int kBlock = plain_block<C>();
     constexpr int64_t kChunk = (int64_t)INT32_MAX / kBlock * kBlock;  // one grid's worth
-    using T = std::conditional_t<C == BOYS_FP64, double, float>;
+    using T = std::conditional_t<C == BOYS_FP32, float, double>;
     for (int64_t off = 0; off < n; off += kChunk) {
         const int64_t cnt = std::min(kChunk, n - off);
         const int grid = (int)((cnt + kBlock - 1) / kBlock);
@@ -265,6 +306,7 @@ constexpr std::array<PlainLaunch, sizeof...(Ns)> plain_table(std::integer_sequen
 
 const auto kPlain64 = plain_table<BOYS_FP64>(std::make_integer_sequence<int, kMaxN64 + 1>{});
 const auto kPlain32 = plain_table<BOYS_FP32>(std::make_integer_sequence<int, kMaxN32 + 1>{});
+const auto kPlain64Plus = plain_table<BOYS_FP64_PLUS>(std::make_integer_sequence<int, kMaxN64>{});
 
 int max_nmax(int32_t prec)
 {
@@ -272,13 +314,15 @@ int max_nmax(int32_t prec)
         return kMaxN64;
     if (prec == BOYS_FP32)
         return kMaxN32;
+    if (prec == BOYS_FP64_PLUS)
+        return kMaxN64 - 1;
     return -1;
 }
 
 boys_status check_array(const double *x, int64_t n, int32_t n_max, const void *out,
                         int64_t ld, int32_t prec)
 {
-    if (prec != BOYS_FP64 && prec != BOYS_FP32)
+    if (prec != BOYS_FP64 && prec != BOYS_FP32 && prec != BOYS_FP64_PLUS)
         return BOYS_ERR_INVALID_ARGUMENT;
     if (n < 0)
         return BOYS_ERR_INVALID_ARGUMENT;
@@ -424,7 +468,7 @@ boys_internal::Launch launch_of(const boys_plan *p)
 
 double tile_cost(const boys_array &a, int64_t cnt)
 {
-    const double bytes = 8.0 + (a.n_max + 1) * (a.precision == BOYS_FP64 ? 8.0 : 4.0);
+    const double bytes = 8.0 + (a.n_max + 1) * (a.precision == BOYS_FP32 ? 4.0 : 8.0);
     return bytes * (double)cnt;
 }
 
@@ -500,6 +544,8 @@ boys_status build_schedule(boys_plan *p, const boys_array *arrays, int32_t count
 
 boys_status capture_graph(boys_plan *p)
 {
+    if (p->ntiles == 0)
+        return BOYS_OK;  // nothing to launch: execute is a no-op
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
         return BOYS_ERR_DEVICE;
@@ -546,8 +592,9 @@ boys_status boys_eval(const double *x, int64_t n, int32_t n_max, void *out, int6
     if (st != BOYS_OK || n == 0)
         return st;
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    const hipError_t err = precision == BOYS_FP64 ? kPlain64[n_max](x, n, out, ld_out, s)
-                                                  : kPlain32[n_max](x, n, out, ld_out, s);
+    const hipError_t err = precision == BOYS_FP64   ? kPlain64[n_max](x, n, out, ld_out, s)
+                           : precision == BOYS_FP32 ? kPlain32[n_max](x, n, out, ld_out, s)
+                                                    : kPlain64Plus[n_max](x, n, out, ld_out, s);
     return err == hipSuccess ? BOYS_OK : BOYS_ERR_DEVICE;
 }
 
@@ -634,6 +681,8 @@ boys_status boys_plan_execute(boys_plan *p, void *stream)
 {
     if (p == nullptr)
         return BOYS_ERR_INVALID_ARGUMENT;
+    if (p->exec == nullptr)
+        return BOYS_OK;  // empty batch
     if (hipGraphLaunch(p->exec, static_cast<hipStream_t>(stream)) != hipSuccess)
         return BOYS_ERR_DEVICE;
     return BOYS_OK;
@@ -717,6 +766,8 @@ double boys_cutoff(int32_t n, int32_t precision)
         return boys_tab::kCut64[n];
     if (precision == BOYS_FP32 && n >= 0 && n <= kMaxN32)
         return boys_tab::kCut32[n];
+    if (precision == BOYS_FP64_PLUS && n >= 0 && n < kMaxN64)
+        return boys_tab::kCut64[n + 1];
     return NAN;
 }
 

@@ -121,16 +121,22 @@ struct Request {
     double t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
 };
 
+// precision classes: 0 binary64, 1 mixed (binary32 output), 2 binary64 (order n+1 trick)
+inline uint64_t elem_size(int32_t prec)
+{
+    return prec == 1 ? 4u : 8u;
+}
+
 // row stride of a request's output: every row starts on a 128-byte boundary
 inline int64_t padded_ld(int64_t n, int32_t prec)
 {
-    const int64_t q = prec == 0 ? 16 : 32;
+    const int64_t q = 128 / (int64_t)elem_size(prec);
     return (n + q - 1) / q * q;
 }
 
 inline uint64_t out_bytes(int64_t n, int32_t n_max, int32_t prec)
 {
-    return (uint64_t)(n_max + 1) * (uint64_t)padded_ld(n, prec) * (prec == 0 ? 8u : 4u);
+    return (uint64_t)(n_max + 1) * (uint64_t)padded_ld(n, prec) * elem_size(prec);
 }
 
 inline uint64_t footprint(int64_t n, int32_t n_max, int32_t prec)
@@ -162,7 +168,7 @@ class Core {
     int submit(int64_t n, int32_t n_max, int32_t prec, const double *x_host, double now,
                uint64_t *id)
     {
-        if (n <= 0 || n_max < 0 || (prec != 0 && prec != 1) || x_host == nullptr)
+        if (n <= 0 || n_max < 0 || prec < 0 || prec > 2 || x_host == nullptr)
             return 1;
         const uint64_t fp = footprint(n, n_max, prec);
         const int64_t tiles = (n + ex_->tile_args() - 1) / ex_->tile_args();

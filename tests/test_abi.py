@@ -68,7 +68,9 @@ def test_queries():
     L = _lib()
     lib = L.lib()
     assert lib.boys_max_nmax(L.FP64) == 36 and lib.boys_max_nmax(L.FP32) == 36
+    assert lib.boys_max_nmax(L.FP64_PLUS) == 35
     assert lib.boys_max_nmax(9) == -1
+    assert lib.boys_cutoff(16, L.FP64_PLUS) == lib.boys_cutoff(17, L.FP64)
     assert abs(lib.boys_cutoff(16, L.FP64) - 74.5) < 0.1
     assert abs(lib.boys_cutoff(16, L.FP32) - 47.6) < 0.1
     assert lib.boys_cutoff(99, L.FP64) != lib.boys_cutoff(99, L.FP64)  # NaN

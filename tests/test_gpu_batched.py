@@ -110,7 +110,9 @@ def test_full_batched_workload_equals_solo():
 def test_every_schedule_equals_solo(tuning):
     torch = require_gpu()
     import paper_2504_07637_amd as boys
-    xs, hs, nm, pr = _batch(torch, 300, 70, nmax_hi=36)
+    xs, hs, nm, pr = _batch(torch, 300, 70, nmax_hi=35)
+    # every third array in the binary64 class with the order n+1 option
+    pr = ["fp64plus" if k % 3 == 0 else p for k, p in enumerate(pr)]
     _say(f"[schedule] {tuning}")
     plan = boys.Plan(xs, nm, pr, tuning=tuning)
     plan.execute()
@@ -136,3 +138,26 @@ def test_autotune_picks_a_candidate(tmp_path, monkeypatch):
     t1, info1 = tuning.tuned(xs, nm, pr, candidates=cands, warmup=1, reps=2)
     t2, info2 = tuning.tuned(xs, nm, pr, candidates=cands)
     assert not info1["cached"] and info2["cached"] and t1 == t2 and t1 in cands
+
+
+def test_empty_arrays_and_empty_batches():
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    x = torch.from_numpy(inputs.integral_args(5000, seed=90)).to("cuda")
+    xs = [x[:0], x[:1000], x[1000:1000], x[1000:5000]]
+    nm, pr = [3, 7, 0, 20], ["fp64", "fp32", "fp64", "fp64plus"]
+    outs = boys.boys_eval_batched(xs, nm, pr)
+    torch.cuda.synchronize()
+    for xi, o, m, p in zip(xs, outs, nm, pr):
+        assert o.shape == (m + 1, xi.numel())
+        if xi.numel():
+            assert torch.equal(o, boys.boys_eval(xi, m, p))
+    # a batch of only empty arrays, and no arrays at all
+    outs = boys.boys_eval_batched([x[:0], x[:0]], [2, 5], ["fp64", "fp32"])
+    assert [o.shape for o in outs] == [(3, 0), (6, 0)]
+    plan = boys.Plan([x[:0]], [4], ["fp64"])
+    plan.execute()
+    plan.close()
+    from paper_2504_07637_amd import _lib
+    assert _lib.lib().boys_eval_batched(None, 0, None) == _lib.OK
+    torch.cuda.synchronize()

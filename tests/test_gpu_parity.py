@@ -42,7 +42,7 @@ def _special():
 def _gpu_eval(torch, x, n, prec, ld_pad=0):
     import paper_2504_07637_amd as boys
     xd = torch.from_numpy(x).to("cuda")
-    dt = torch.float64 if prec == "fp64" else torch.float32
+    dt = torch.float32 if prec == "fp32" else torch.float64
     if ld_pad:
         buf = torch.full((n + 1, x.size + ld_pad), -7.0, dtype=dt, device="cuda")
         out = buf[:, : x.size]
@@ -62,7 +62,16 @@ def _mixed_inputs(seed):
                            _special()])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def _oracle(x, n, prec):
+    if prec == "fp64":
+        return orc.approx_f64(x, n)
+    if prec == "fp32":
+        return orc.approx_mixed(x, n)
+    # the order n+1 option: the oracle's order n+1 evaluation without its top row
+    return orc.approx_f64(x, n + 1)[: n + 1]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64plus"])
 def test_identical_to_the_oracle_every_nmax(prec):
     torch = require_gpu()
     import paper_2504_07637_amd as boys
@@ -70,7 +79,7 @@ def test_identical_to_the_oracle_every_nmax(prec):
     for n in range(boys.max_nmax(prec) + 1):
         _say(f"[parity] {prec} n_max={n} count={x.size}")
         got = _gpu_eval(torch, x, n, prec)
-        want = orc.approx_f64(x, n) if prec == "fp64" else orc.approx_mixed(x, n)
+        want = _oracle(x, n, prec)
         msg = report_mismatch(f"{prec} n_max={n}", got, want)
         assert not msg, msg
 
@@ -85,6 +94,31 @@ def _bounds(table1, cls, n):
         out[n - 1] = ebn1 - 1.0
     out[n] = ebn - 1.0
     return out
+
+
+@pytest.mark.parametrize("n", [1, 4, 16, 20, 35])
+def test_order_plus_one_option_error_and_gain(n, table1):
+    # F_n by one recursion step from the order n+1 approximant: every m within the
+    # Table 1 finite-precision bounds of row n+1 (F_n is that row's F_{n-1} column), and
+    # F_n itself not less accurate than the plain order-n evaluation
+    torch = require_gpu()
+    r = orc.record("fp64", n + 1)
+    k = 1 << 15
+    x = np.concatenate([np.arange(k) * (r["z"] / k), inputs.integral_args(1 << 15, seed=33)])
+    _say(f"[plus] n_max={n} count={x.size}")
+    plus = _gpu_eval(torch, x, n, "fp64plus")
+    base = _gpu_eval(torch, x, n, "fp64")
+    hi, lo = orc.exact(x, n)
+    t = table1[n + 1]["fp64"]
+    bound_n = t["ebn1"] - 1.0
+    bound_low = min(t["eb0"], t["ebn1"]) - 1.0
+    for m in range(n + 1):
+        b = orc.bits(orc.rel_err(plus[m], hi[m], lo[m]))
+        assert b >= (bound_n if m == n else bound_low), (n, m, b)
+    gain = (orc.bits(orc.rel_err(plus[n], hi[n], lo[n]))
+            - orc.bits(orc.rel_err(base[n], hi[n], lo[n])))
+    _say(f"[plus] n_max={n} F_n gain {gain:.2f} bits")
+    assert gain > (1.0 if n >= 4 else -0.5)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -117,11 +151,10 @@ def test_error_against_exact_function_within_table1(prec, n, table1):
 def test_ragged_lengths_and_padded_rows(n):
     torch = require_gpu()
     x = inputs.integral_args(n, seed=n)
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "fp64plus"):
         _say(f"[ragged] {prec} n={n}")
         got = _gpu_eval(torch, x, 7, prec, ld_pad=37)
-        want = orc.approx_f64(x, 7) if prec == "fp64" else orc.approx_mixed(x, 7)
-        assert same_bits(got, want).all()
+        assert same_bits(got, _oracle(x, 7, prec)).all()
 
 
 def test_empty_input_is_a_noop():
