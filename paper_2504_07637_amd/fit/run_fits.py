@@ -5,13 +5,15 @@ Usage:  python -m paper_2504_07637_amd.fit.run_fits [--nmax 36] [--jobs 7] [--ou
 The orders N follow Table 1 of the paper (blank cells read as repeats of the cell
 above): binary64 N = 10 (n = 0-1), 11 (2-6), 12 (7-10), 13 (11-17), 14 (18-36);
 binary32 N = 4 (0-1), 5 (2-9), 6 (10-36).  The cut-off z_nb uses b = 53 for the
-binary64 class and b = 24 for the binary32 class.
+binary64 class and b = 24 for the binary32 class.  The class fp32x (binary32 results
+rounded from binary64 arithmetic) uses b = 28 and, per n, the smallest N whose fit
+reaches 28 bits; its coefficients are binary64 values.
 
 Dataset format (text, one token list per line, '#' starts a comment):
 
     format boys-coeffs 1
     c0 <hex>                         c_0 = sqrt(pi)/2 in binary64
-    record <fp64|fp32> <n> <N>
+    record <fp64|fp32|fp32x> <n> <N>
     c  <hex> <dec>                   c_n (binary64)
     z  <hex> <dec>                   z_nb (binary64)
     q0 <hex> <dec>                   Q_n(0)        } working precision of the class
@@ -51,6 +53,17 @@ def table1_N(cls: str, n: int) -> int:
     return 4 if n <= 1 else 5 if n <= 9 else 6
 
 
+# the binary32-output class evaluated in binary64 (section "Computations": full 24-bit
+# binary32 values by rounding binary64 results of about 28-bit approximants): cut-off
+# b = 28 and the smallest N whose fit reaches EPS_FP32X bits
+B_FP32X = 28
+EPS_FP32X = 28.0
+
+
+def class_b(cls: str) -> int:
+    return {"fp64": 53, "fp32": 24, "fp32x": B_FP32X}[cls]
+
+
 def _record_from(cls, n, N, b, A, B, z, t0, extra=None):
     cn = bf.consts(n)
     f = bf.factor(cn, A, B)
@@ -62,10 +75,10 @@ def _record_from(cls, n, N, b, A, B, z, t0, extra=None):
     for y, a in f.uq + f.vq:
         if a <= 0:
             raise RuntimeError("non-positive a in a quadratic factor")
-    fr = bf.round_factored(f, cls == "fp32")
+    fr = bf.round_factored(f, cls == "fp32")  # fp32x coefficients are binary64 values
     eps_x = bf.dense_error(n, f, z, npts=1500)
     eps_r = bf.dense_error(n, fr, z, npts=1500)
-    to_hex = bf.to_f32_hex if cls == "fp32" else (lambda v: bf.hexf(float(v)))
+    to_hex = bf.to_f32_hex if cls == "fp32" else (lambda v: bf.hexf(float(v)))  # fp32x: binary64
     rec = {
         "cls": cls, "n": n, "N": N, "b": b,
         "c": (bf.hexf(float(cn.c)), bf.decs(cn.c)),
@@ -92,8 +105,10 @@ def _record_from(cls, n, N, b, A, B, z, t0, extra=None):
 def _fit_one(job):
     """Lawson-SK fit from scratch, then the Remez polish."""
     cls, n = job
+    if cls == "fp32x":
+        return _fit_adaptive(n)
     mp.mp.prec = bf.PREC
-    b = 53 if cls == "fp64" else 24
+    b = class_b(cls)
     N = table1_N(cls, n)
     t0 = time.time()
     attempts = [(500 if cls == "fp64" else 300, 1.0), (800, 1.0), (800, 1.1)]
@@ -120,11 +135,38 @@ def _fit_one(job):
     return rec
 
 
+def _fit_adaptive(n: int):
+    """fp32x: the smallest N (from 4 up) whose polished fit reaches EPS_FP32X bits."""
+    mp.mp.prec = bf.PREC
+    cls, b = "fp32x", B_FP32X
+    t0 = time.time()
+    last = None
+    for N in range(4, 11):
+        try:
+            r = bf.fit(n, N, b, M=300, iters=300)
+            A, B = r.A, r.B
+            try:
+                A, B, _ = bf.remez_polish(n, N, b, A, B, M=1500, iters=40)
+            except Exception:
+                pass
+            rec = _record_from(cls, n, N, b, A, B, r.z, t0)
+        except Exception as exc:
+            last = {"cls": cls, "n": n, "N": N, "error": repr(exc)}
+            continue
+        last = rec
+        if rec["eps_exact"] >= EPS_FP32X:
+            break
+    if "error" not in last:
+        print(f"[fit] {cls} n={n} N={last['N']} eps={last['eps_exact']:.2f} "
+              f"(rounded {last['eps_rounded']:.2f}) {time.time() - t0:.0f}s", flush=True)
+    return last
+
+
 def _polish_one(job):
     """Remez polish of an existing dataset entry; keeps the better of the two."""
     cls, n, N, A, B, eps_old = job
     mp.mp.prec = bf.PREC
-    b = 53 if cls == "fp64" else 24
+    b = class_b(cls)
     t0 = time.time()
     z = bf.cutoff(n, b)
     A = [mp.mpf(a) for a in A]
@@ -171,7 +213,23 @@ def _pairs(tag, pairs):
     return f"{tag} {len(pairs)}" + "".join(f" {a} {b}" for a, b in pairs)
 
 
-def write_dataset(records, path):
+def read_blocks(path):
+    """[(cls, n, text)] of the record blocks of an existing dataset file."""
+    out, cur, lines = [], None, []
+    with open(path) as fh:
+        for raw in fh:
+            tok = raw.split()
+            if tok and tok[0] == "record":
+                cur, lines = (tok[1], int(tok[2])), [raw.rstrip("\n")]
+            elif cur is not None:
+                lines.append(raw.rstrip("\n"))
+                if tok and tok[0] == "end":
+                    out.append((cur[0], cur[1], "\n".join(lines)))
+                    cur = None
+    return out
+
+
+def write_dataset(records, path, kept_blocks=()):
     mp.mp.prec = bf.PREC
     c0 = mp.sqrt(mp.pi) / 2
     out = ["# Boys-function approximant coefficients (root-factored form of Eqs. pqz, pz, qz)",
@@ -194,6 +252,7 @@ def write_dataset(records, path):
         out.append(_line("B", r["B"]))
         out.append(f"eps {r['eps_exact']:.3f} {r['eps_rounded']:.3f}")
         out.append("end")
+    out.extend(kept_blocks)
     with open(path, "w") as fh:
         fh.write("\n".join(out) + "\n")
 
@@ -207,6 +266,8 @@ def main(argv=None):
     ap.add_argument("--report", default=REPORT)
     ap.add_argument("--polish", action="store_true",
                     help="polish the existing dataset at --out instead of fitting afresh")
+    ap.add_argument("--merge", action="store_true",
+                    help="keep the records of other classes already in --out")
     args = ap.parse_args(argv)
     classes = args.classes.split(",")
     if args.polish:
@@ -224,7 +285,14 @@ def main(argv=None):
             recs = pool.map(_fit_one, jobs, chunksize=1)
     bad = [r for r in recs if "error" in r]
     good = [r for r in recs if "error" not in r]
-    write_dataset(good, args.out)
+    if args.merge and os.path.exists(args.out):
+        kept = [blk for blk in read_blocks(args.out) if blk[0] not in classes]
+        write_dataset(good, args.out, kept_blocks=[b for _, _, b in kept])
+        if os.path.exists(args.report):
+            old_rep = [r for r in json.load(open(args.report)) if r["cls"] not in classes]
+            recs = old_rep + recs
+    else:
+        write_dataset(good, args.out)
     with open(args.report, "w") as fh:
         json.dump([{k: r[k] for k in r if k in ("cls", "n", "N", "eps_exact", "eps_rounded",
                                                 "eps_sampled", "iterations", "seconds", "error")}
