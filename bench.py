@@ -110,7 +110,7 @@ def accuracy(torch, boys, xd, x):
     ti = torch.from_numpy(idx).to(xd.device)
     out = {}
     hi, lo = orc.exact(x[idx], N_MAX)
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "fp32x"):
         F = boys.boys_eval(xd, N_MAX, prec)[:, ti].double().cpu().numpy()
         per_m = []
         for m in range(N_MAX + 1):
@@ -222,6 +222,8 @@ def main():
                           args.steps, args.warmup)
     wall32, gpu32 = timed(torch, lambda: boys.boys_eval(xd, N_MAX, "fp32", out=out32),
                           args.steps, args.warmup)
+    wall32x, gpu32x = timed(torch, lambda: boys.boys_eval(xd, N_MAX, "fp32x", out=out32),
+                            args.steps, args.warmup)
     values = (N_MAX + 1) * N_ARGS
     ms64 = wall64 / args.steps * 1e3
     v64 = values * args.steps / wall64
@@ -255,6 +257,11 @@ def main():
                  "speedup_vs_fp64": v32 / v64,
                  "launch_ms": gpu32 / args.steps * 1e3,
                  "hbm_GBs": (8 + 4 * (N_MAX + 1)) * N_ARGS / (gpu32 / args.steps) / 1e9},
+        "fp32x": {"value": values * args.steps / wall32x, "unit": "values/s",
+                  "ms_per_step": wall32x / args.steps * 1e3,
+                  "speedup_vs_fp64": wall64 / wall32x,
+                  "launch_ms": gpu32x / args.steps * 1e3,
+                  "hbm_GBs": (8 + 4 * (N_MAX + 1)) * N_ARGS / (gpu32x / args.steps) / 1e9},
     }
     del out32
     torch.cuda.empty_cache()

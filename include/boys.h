@@ -22,7 +22,7 @@
  *   - x is binary64, contiguous, n elements.
  *   - out holds (n_max + 1) rows of ld_out elements: F_m(x[i]) is at out[m * ld_out + i]
  *     (structure of arrays), binary64 for BOYS_FP64 / BOYS_FP64_PLUS and binary32 for
- *     BOYS_FP32.
+ *     BOYS_FP32 / BOYS_FP32X.
  *     Requires ld_out >= n.  Alignment: 8 bytes (FP64) or 4 bytes (FP32).  Rows that
  *     start on 128-byte boundaries (out 128-byte aligned and ld_out a multiple of 16
  *     binary64 / 32 binary32 elements) are written as whole cache lines; other strides
@@ -56,7 +56,13 @@ typedef enum {
        the order n_max+1 approximant (and its cut-off z_{n_max+1,53}) gives F_{n_max+1},
        one more step of Eq. r gives F_{n_max}, which is not stored; output binary64
        (F_{n_max} gains about 3 bits at n_max >= 16); n_max <= boys_max_nmax - 1 */
-    BOYS_FP64_PLUS = 2
+    BOYS_FP64_PLUS = 2,
+    /* binary32 output at full single-precision accuracy, as the paper suggests for it:
+       binary64 arithmetic throughout with approximants fitted to about 28 bits (the
+       smallest N per n reaching 28 bits) and the cut-off z_{n_max,28}; each value is
+       rounded once to binary32 at the store, so its error is within half a binary32 ulp
+       plus 2^-28 relative (subnormal outputs: plus half the subnormal spacing) */
+    BOYS_FP32X = 3
 } boys_precision;
 
 typedef enum {
@@ -71,7 +77,7 @@ typedef enum {
  * Evaluate F_m(x[i]) for m = 0..n_max and i = 0..n-1 into out (layout above).
  * precision is a boys_precision value.  The approximant of order n_max is used
  * (coefficient set fitted for that n and that precision class, with the cut-off
- * z_{n_max,b}, b = 53 for BOYS_FP64 and 24 for BOYS_FP32), and the lower orders come
+ * z_{n_max,b}, b = 53 for BOYS_FP64, 24 for BOYS_FP32, 28 for BOYS_FP32X), and the lower orders come
  * from the downward recursion of Eq. r below the cut-off and from Eq. limf1 above it.
  */
 boys_status boys_eval(const double *x, int64_t n, int32_t n_max, void *out, int64_t ld_out,

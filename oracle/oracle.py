@@ -13,6 +13,8 @@ exact_one(x, m)           the same for one order m, arrays of shape (len(x),).
 approx_f64(x, n)          the binary64 approximant (Eqs. fq, pqz, pz, qz, r, limf1),
                           shape (n+1, len(x)), float64.
 approx_mixed(x, n)        the mixed binary32/binary64 class, shape (n+1, len(x)), float32.
+approx_f32x(x, n)         the binary32-output class computed in binary64 (the ~28-bit
+                          approximant, each value rounded once), shape (n+1, len(x)), float32.
 approx_exact_n(x, n)      F~_n in binary128 from the 40-digit coefficients, as (hi, lo).
 exp_neg(x)                correctly rounded exp(-x) as both approximants use it.
 load_dataset(path)        the parsed coefficient dataset.
@@ -246,6 +248,13 @@ def approx_mixed(x, n: int, rec: Record | None = None):
     if rc:
         raise ValueError("oracle_boys_approx_mixed rejected its arguments")
     return out
+
+
+def approx_f32x(x, n: int, rec: Record | None = None):
+    """The binary64 evaluation of the ~28-bit approximant (same steps as approx_f64, the
+    record's own cut-off), each value rounded to nearest binary32 once at the end."""
+    r = rec if rec is not None else record("fp32x", n)
+    return approx_f64(x, n, r).astype(np.float32)
 
 
 def approx_exact_n(x, n: int, cls: str = "fp64", fields=None):

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(PKG, "libboys.so")
 FP64 = 0
 FP32 = 1
 FP64_PLUS = 2
+FP32X = 3
 
 OK = 0
 ERR_INVALID_ARGUMENT = 1

@@ -253,11 +253,10 @@ __host__ __device__ __forceinline__ T factors(T x, const T (&g)[NG > 0 ? NG : 1]
 // ---------------------------------------------------------------------------------
 // F_0..F_N for one argument, binary64 class
 
-template <int N>
-__host__ __device__ __forceinline__ void eval_f64(double x, const double2 *__restrict__ tab,
-                                                  double (&F)[N + 1])
+template <class S, int N>
+__host__ __device__ __forceinline__ void eval_f64_set(double x, const double2 *__restrict__ tab,
+                                                      double (&F)[N + 1])
 {
-    using S = boys_tab::F64Set<N>;
     if (!(x > S::z)) {
         // below the cut-off (NaN and negative x also pass here and are replaced below)
         const double e = exp_rn(__builtin_fmax(-x, -120.0), tab);
@@ -285,6 +284,23 @@ __host__ __device__ __forceinline__ void eval_f64(double x, const double2 *__res
         for (int m = 0; m <= N; ++m)
             F[m] = __builtin_nan("");
     }
+}
+
+// the binary64 class: Table 1's binary64 approximants, cut-off z_{n,53}
+template <int N>
+__host__ __device__ __forceinline__ void eval_f64(double x, const double2 *__restrict__ tab,
+                                                  double (&F)[N + 1])
+{
+    eval_f64_set<boys_tab::F64Set<N>, N>(x, tab, F);
+}
+
+// the binary32-output class computed in binary64: approximants of about 28 bits with the
+// cut-off z_{n,28}, every value rounded once to binary32 (by the caller)
+template <int N>
+__host__ __device__ __forceinline__ void eval_f32r(double x, const double2 *__restrict__ tab,
+                                                   double (&F)[N + 1])
+{
+    eval_f64_set<boys_tab::F32xSet<N>, N>(x, tab, F);
 }
 
 // ---------------------------------------------------------------------------------

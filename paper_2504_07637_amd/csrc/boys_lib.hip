@@ -36,8 +36,10 @@ namespace {
 
 using boys_tab::kMaxN32;
 using boys_tab::kMaxN64;
+using boys_tab::kMaxN32x;
 
-constexpr int kMaxN = kMaxN64 > kMaxN32 ? kMaxN64 : kMaxN32;
+constexpr int kMaxN = kMaxN64 > kMaxN32 ? (kMaxN64 > kMaxN32x ? kMaxN64 : kMaxN32x)
+                                        : (kMaxN32 > kMaxN32x ? kMaxN32 : kMaxN32x);
 
 // ---------------------------------------------------------------------------------
 // device code
@@ -75,7 +77,20 @@ __device__ __forceinline__ void body_f64plus(const double *__restrict__ x,
         __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
 }
 
-// one argument of class C (BOYS_FP64, BOYS_FP32 or BOYS_FP64_PLUS) at order N
+// binary32 output from binary64 arithmetic with the ~28-bit approximants; each value is
+// rounded once to binary32 at the store
+template <int N>
+__device__ __forceinline__ void body_f32x(const double *__restrict__ x, float *__restrict__ out,
+                                          int64_t ld, int64_t i, const double2 *tab)
+{
+    double F[N + 1];
+    boys::eval_f32r<N>(__builtin_nontemporal_load(x + i), tab, F);
+#pragma unroll
+    for (int m = 0; m <= N; ++m)
+        __builtin_nontemporal_store((float)F[m], out + (int64_t)m * ld + i);
+}
+
+// one argument of class C (a boys_precision value) at order N
 template <int C, int N>
 __device__ __forceinline__ void body(const Desc &d, int64_t i, const double2 *tab);
 
@@ -106,7 +121,8 @@ constexpr int plain_block()
 template <int C>
 constexpr int class_max()
 {
-    return C == BOYS_FP32 ? kMaxN32 : C == BOYS_FP64 ? kMaxN64 : kMaxN64 - 1;
+    return C == BOYS_FP32 ? kMaxN32 : C == BOYS_FP64 ? kMaxN64 : C == BOYS_FP32X ? kMaxN32x
+                                                                            : kMaxN64 - 1;
 }
 
 template <int C, int N>
@@ -116,6 +132,8 @@ __device__ __forceinline__ void body(const Desc &d, int64_t i, const double2 *ta
         body_f64<N>(d.x, static_cast<double *>(d.out), d.ld, i, tab);
     else if constexpr (C == BOYS_FP64_PLUS)
         body_f64plus<N>(d.x, static_cast<double *>(d.out), d.ld, i, tab);
+    else if constexpr (C == BOYS_FP32X)
+        body_f32x<N>(d.x, static_cast<float *>(d.out), d.ld, i, tab);
     else
         body_f32<N>(d.x, static_cast<float *>(d.out), d.ld, i, tab);
 }
@@ -141,6 +159,8 @@ __global__ __launch_bounds__(plain_block<C>()) void k_plain(const double *__rest
             body_f64<N>(x, static_cast<double *>(out), ld, i, tab);
         else if constexpr (C == BOYS_FP64_PLUS)
             body_f64plus<N>(x, static_cast<double *>(out), ld, i, tab);
+        else if constexpr (C == BOYS_FP32X)
+            body_f32x<N>(x, static_cast<float *>(out), ld, i, tab);
         else
             body_f32<N>(x, static_cast<float *>(out), ld, i, tab);
     }
@@ -195,6 +215,8 @@ __global__ __launch_bounds__(256) void k_batched(const Desc *__restrict__ descs,
             dispatch_n<BOYS_FP64, cmin(MAXN, class_max<BOYS_FP64>())>(n, d, start, cnt, tab);
         else if (prec == BOYS_FP32)
             dispatch_n<BOYS_FP32, cmin(MAXN, class_max<BOYS_FP32>())>(n, d, start, cnt, tab);
+        else if (prec == BOYS_FP32X)
+            dispatch_n<BOYS_FP32X, cmin(MAXN, class_max<BOYS_FP32X>())>(n, d, start, cnt, tab);
         else
             dispatch_n<BOYS_FP64_PLUS, cmin(MAXN, class_max<BOYS_FP64_PLUS>())>(n, d, start, cnt,
                                                                                  tab);
@@ -246,6 +268,8 @@ __global__ __launch_bounds__(256) void k_batched_wg(const Desc *__restrict__ des
     } else if (prec == BOYS_FP32) {
         load_exp_table(lds_tab);
         dispatch_wg<BOYS_FP32, cmin(MAXN, class_max<BOYS_FP32>()), K>(n, d, start, lds_tab);
+    } else if (prec == BOYS_FP32X) {
+        dispatch_wg<BOYS_FP32X, cmin(MAXN, class_max<BOYS_FP32X>()), K>(n, d, start, gtab);
     } else {
         dispatch_wg<BOYS_FP64_PLUS, cmin(MAXN, class_max<BOYS_FP64_PLUS>()), K>(n, d, start, gtab);
     }
@@ -285,7 +309,7 @@ hipError_t launch_plain(const double *x, int64_t n, void *out, int64_t ld, hipSt
 {
     constexpr int kBlock = plain_block<C>();
     constexpr int64_t kChunk = (int64_t)INT32_MAX / kBlock * kBlock;  // one grid's worth
-    using T = std::conditional_t<C == BOYS_FP32, float, double>;
+    using T = std::conditional_t<C == BOYS_FP32 || C == BOYS_FP32X, float, double>;
     for (int64_t off = 0; off < n; off += kChunk) {
         const int64_t cnt = std::min(kChunk, n - off);
         const int grid = (int)((cnt + kBlock - 1) / kBlock);
@@ -307,6 +331,7 @@ constexpr std::array<PlainLaunch, sizeof...(Ns)> plain_table(std::integer_sequen
 const auto kPlain64 = plain_table<BOYS_FP64>(std::make_integer_sequence<int, kMaxN64 + 1>{});
 const auto kPlain32 = plain_table<BOYS_FP32>(std::make_integer_sequence<int, kMaxN32 + 1>{});
 const auto kPlain64Plus = plain_table<BOYS_FP64_PLUS>(std::make_integer_sequence<int, kMaxN64>{});
+const auto kPlain32x = plain_table<BOYS_FP32X>(std::make_integer_sequence<int, kMaxN32x + 1>{});
 
 int max_nmax(int32_t prec)
 {
@@ -316,13 +341,20 @@ int max_nmax(int32_t prec)
         return kMaxN32;
     if (prec == BOYS_FP64_PLUS)
         return kMaxN64 - 1;
+    if (prec == BOYS_FP32X)
+        return kMaxN32x;
     return -1;
+}
+
+int elem_bytes(int32_t prec)
+{
+    return prec == BOYS_FP32 || prec == BOYS_FP32X ? 4 : 8;
 }
 
 boys_status check_array(const double *x, int64_t n, int32_t n_max, const void *out,
                         int64_t ld, int32_t prec)
 {
-    if (prec != BOYS_FP64 && prec != BOYS_FP32 && prec != BOYS_FP64_PLUS)
+    if (max_nmax(prec) < 0)
         return BOYS_ERR_INVALID_ARGUMENT;
     if (n < 0)
         return BOYS_ERR_INVALID_ARGUMENT;
@@ -468,7 +500,7 @@ boys_internal::Launch launch_of(const boys_plan *p)
 
 double tile_cost(const boys_array &a, int64_t cnt)
 {
-    const double bytes = 8.0 + (a.n_max + 1) * (a.precision == BOYS_FP32 ? 4.0 : 8.0);
+    const double bytes = 8.0 + (a.n_max + 1) * (elem_bytes(a.precision) * 1.0);
     return bytes * (double)cnt;
 }
 
@@ -594,7 +626,8 @@ boys_status boys_eval(const double *x, int64_t n, int32_t n_max, void *out, int6
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const hipError_t err = precision == BOYS_FP64   ? kPlain64[n_max](x, n, out, ld_out, s)
                            : precision == BOYS_FP32 ? kPlain32[n_max](x, n, out, ld_out, s)
-                                                    : kPlain64Plus[n_max](x, n, out, ld_out, s);
+                           : precision == BOYS_FP32X ? kPlain32x[n_max](x, n, out, ld_out, s)
+                                                     : kPlain64Plus[n_max](x, n, out, ld_out, s);
     return err == hipSuccess ? BOYS_OK : BOYS_ERR_DEVICE;
 }
 
@@ -768,6 +801,8 @@ double boys_cutoff(int32_t n, int32_t precision)
         return boys_tab::kCut32[n];
     if (precision == BOYS_FP64_PLUS && n >= 0 && n < kMaxN64)
         return boys_tab::kCut64[n + 1];
+    if (precision == BOYS_FP32X && n >= 0 && n <= kMaxN32x)
+        return boys_tab::kCut32x[n];
     return NAN;
 }
 

@@ -82,7 +82,7 @@ struct HipExec {
                                 r.n_max, r.prec};
             maxn = std::max(maxn, r.n_max);
             const int64_t nt = (r.n + tile - 1) / tile;
-            const double per = 8.0 + (r.n_max + 1) * (r.prec == BOYS_FP32 ? 4.0 : 8.0);
+            const double per = 8.0 + (r.n_max + 1) * (double)boys_serve::elem_size(r.prec);
             for (int64_t k = 0; k < nt; ++k) {
                 const int64_t cnt = std::min<int64_t>(tile, r.n - k * tile);
                 ts.push_back({per * (double)cnt, a, (int32_t)k});
@@ -255,7 +255,7 @@ boys_status boys_server_submit(boys_server *s, const double *x_host, int64_t n, 
 {
     if (s == nullptr || id == nullptr)
         return BOYS_ERR_INVALID_ARGUMENT;
-    if (precision != BOYS_FP64 && precision != BOYS_FP32 && precision != BOYS_FP64_PLUS)
+    if (boys_max_nmax(precision) < 0)
         return BOYS_ERR_INVALID_ARGUMENT;
     if (n_max < 0 || n_max > boys_max_nmax(precision))
         return BOYS_ERR_UNSUPPORTED_NMAX;
@@ -314,7 +314,7 @@ boys_status boys_server_copy_result(boys_server *s, uint64_t id, void *dst, int6
         const Request *r = s->core->find(id);
         if (r == nullptr || r->state != boys_serve::State::Done || ld_dst < r->n)
             return BOYS_ERR_INVALID_ARGUMENT;
-        const size_t es = r->prec == BOYS_FP32 ? 4 : 8;
+        const size_t es = boys_serve::elem_size(r->prec);
         src = s->ex.pool_base + r->off + r->x_bytes;
         width = (size_t)r->n * es;
         spitch = (size_t)r->ld * es;

@@ -45,6 +45,7 @@ def test_argument_errors_are_reported_before_any_launch():
     assert lib.boys_eval(fake, 10, 4, fake, 9, L.FP64, None) == L.ERR_INVALID_ARGUMENT
     assert lib.boys_eval(fake, -1, 4, fake, 10, L.FP64, None) == L.ERR_INVALID_ARGUMENT
     assert lib.boys_eval(fake, 10, 4, fake, 10, 7, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eval(fake, 10, 4, fake, 10, 4, None) == L.ERR_INVALID_ARGUMENT
     assert lib.boys_eval(fake, 10, -1, fake, 10, L.FP64, None) == L.ERR_UNSUPPORTED_NMAX
     big = lib.boys_max_nmax(L.FP64) + 1
     assert lib.boys_eval(fake, 10, big, fake, 10, L.FP64, None) == L.ERR_UNSUPPORTED_NMAX
@@ -69,7 +70,11 @@ def test_queries():
     lib = L.lib()
     assert lib.boys_max_nmax(L.FP64) == 36 and lib.boys_max_nmax(L.FP32) == 36
     assert lib.boys_max_nmax(L.FP64_PLUS) == 35
-    assert lib.boys_max_nmax(9) == -1
+    assert lib.boys_max_nmax(L.FP32X) == 36
+    assert lib.boys_max_nmax(9) == -1 and lib.boys_max_nmax(4) == -1
+    for n in (0, 16, 36):
+        # z_{n,24} < z_{n,28} < z_{n,53}
+        assert lib.boys_cutoff(n, L.FP32) < lib.boys_cutoff(n, L.FP32X) < lib.boys_cutoff(n, L.FP64)
     assert lib.boys_cutoff(16, L.FP64_PLUS) == lib.boys_cutoff(17, L.FP64)
     assert abs(lib.boys_cutoff(16, L.FP64) - 74.5) < 0.1
     assert abs(lib.boys_cutoff(16, L.FP32) - 47.6) < 0.1

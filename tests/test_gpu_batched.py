@@ -111,8 +111,10 @@ def test_every_schedule_equals_solo(tuning):
     torch = require_gpu()
     import paper_2504_07637_amd as boys
     xs, hs, nm, pr = _batch(torch, 300, 70, nmax_hi=35)
-    # every third array in the binary64 class with the order n+1 option
-    pr = ["fp64plus" if k % 3 == 0 else p for k, p in enumerate(pr)]
+    # every third array in the binary64 class with the order n+1 option, every fifth
+    # in the binary32-output class computed in binary64
+    pr = ["fp64plus" if k % 3 == 0 else "fp32x" if k % 5 == 0 else p
+          for k, p in enumerate(pr)]
     _say(f"[schedule] {tuning}")
     plan = boys.Plan(xs, nm, pr, tuning=tuning)
     plan.execute()
@@ -145,7 +147,7 @@ def test_empty_arrays_and_empty_batches():
     import paper_2504_07637_amd as boys
     x = torch.from_numpy(inputs.integral_args(5000, seed=90)).to("cuda")
     xs = [x[:0], x[:1000], x[1000:1000], x[1000:5000]]
-    nm, pr = [3, 7, 0, 20], ["fp64", "fp32", "fp64", "fp64plus"]
+    nm, pr = [3, 7, 0, 20], ["fp64", "fp32x", "fp64", "fp64plus"]
     outs = boys.boys_eval_batched(xs, nm, pr)
     torch.cuda.synchronize()
     for xi, o, m, p in zip(xs, outs, nm, pr):

@@ -42,7 +42,7 @@ def _special():
 def _gpu_eval(torch, x, n, prec, ld_pad=0):
     import paper_2504_07637_amd as boys
     xd = torch.from_numpy(x).to("cuda")
-    dt = torch.float32 if prec == "fp32" else torch.float64
+    dt = torch.float32 if prec in ("fp32", "fp32x") else torch.float64
     if ld_pad:
         buf = torch.full((n + 1, x.size + ld_pad), -7.0, dtype=dt, device="cuda")
         out = buf[:, : x.size]
@@ -67,11 +67,13 @@ def _oracle(x, n, prec):
         return orc.approx_f64(x, n)
     if prec == "fp32":
         return orc.approx_mixed(x, n)
+    if prec == "fp32x":
+        return orc.approx_f32x(x, n)
     # the order n+1 option: the oracle's order n+1 evaluation without its top row
     return orc.approx_f64(x, n + 1)[: n + 1]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64plus"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64plus", "fp32x"])
 def test_identical_to_the_oracle_every_nmax(prec):
     torch = require_gpu()
     import paper_2504_07637_amd as boys
@@ -147,14 +149,36 @@ def test_error_against_exact_function_within_table1(prec, n, table1):
          " ".join(f"{b:.1f}" for b in measured))
 
 
-@pytest.mark.parametrize("n", [1, 63, 64, 65, 255, 257, 4099, 100003])
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 255, 257, 4099, 100003])
 def test_ragged_lengths_and_padded_rows(n):
     torch = require_gpu()
     x = inputs.integral_args(n, seed=n)
-    for prec in ("fp64", "fp32", "fp64plus"):
+    for prec in ("fp64", "fp32", "fp64plus", "fp32x"):
         _say(f"[ragged] {prec} n={n}")
         got = _gpu_eval(torch, x, 7, prec, ld_pad=37)
         assert same_bits(got, _oracle(x, 7, prec)).all()
+
+
+@pytest.mark.parametrize("n", [0, 1, 4, 16, 20, 36])
+def test_fp32x_within_half_a_binary32_ulp_of_the_exact_function(n):
+    # binary32 outputs computed in binary64 with the ~28-bit approximant: within half a
+    # binary32 ulp plus 2^-27.5 relative of the exact F_m (subnormals: of FLT_MIN)
+    torch = require_gpu()
+    r = orc.record("fp32x", n)
+    k = 1 << 15
+    x = np.concatenate([np.arange(k) * (r["z"] / k), inputs.integral_args(1 << 15, seed=35)])
+    _say(f"[exact] fp32x n_max={n} count={x.size}")
+    got = _gpu_eval(torch, x, n, "fp32x")
+    hi, lo = orc.exact(x, n)
+    rounded = 0
+    for m in range(n + 1):
+        F = hi[m] + lo[m]
+        err = np.abs(got[m].astype(np.float64) - hi[m] - lo[m])
+        half_ulp = 0.5 * np.spacing(np.abs(F).astype(np.float32)).astype(np.float64)
+        tol = half_ulp + 2.0 ** -27.5 * np.maximum(np.abs(F), FLT_MIN)
+        assert np.all(err <= tol), (n, m, float(np.max(err / tol)))
+        rounded += int(np.sum(got[m] == F.astype(np.float32)))
+    _say(f"[exact] fp32x n_max={n} correctly rounded: {rounded / (x.size * (n + 1)):.5f}")
 
 
 def test_empty_input_is_a_noop():

@@ -89,6 +89,28 @@ def test_past_the_cutoff_and_large_arguments(cls, b):
         assert A[0, -1] > 0  # F_0(1e30) = sqrt(pi)/2e15 is not lost to underflow
 
 
+@pytest.mark.parametrize("n", NS)
+def test_fp32x_class_within_half_a_binary32_ulp(n):
+    # binary32 outputs computed in binary64 from the ~28-bit approximant: every normal
+    # value within half a binary32 ulp plus 2^-27.5 relative of the exact F_m, below and
+    # above the cut-off z_{n,28}; subnormal outputs within half the subnormal spacing plus
+    # 2^-27.5 of FLT_MIN
+    r = orc.record("fp32x", n)
+    k = 1 << 14
+    x = np.concatenate([np.arange(k) * (r["z"] / k),
+                        r["z"] * (1.0 + np.arange(1, 257) / 64.0), [1e3, 1e6, 1e12]])
+    A = orc.approx_f32x(x, n)
+    hi, lo = orc.exact(x, n)
+    fmin = 1.1754943508222875e-38
+    for m in range(n + 1):
+        F = hi[m] + lo[m]
+        err = np.abs(A[m].astype(np.float64) - hi[m] - lo[m])
+        half_ulp = 0.5 * np.spacing(np.abs(F).astype(np.float32)).astype(np.float64)
+        tol = half_ulp + 2.0 ** -27.5 * np.maximum(np.abs(F), fmin)
+        bad = np.nonzero(err > tol)[0]
+        assert bad.size == 0, (n, m, x[bad[:3]], err[bad[:3]], tol[bad[:3]])
+
+
 def test_pin_detects_planted_mistakes():
     # a wrong q1, or swapping the gathered factors of u and v, breaks the Table 1 pin
     r = orc.record("fp64", 16)
