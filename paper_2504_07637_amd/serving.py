@@ -127,7 +127,7 @@ def argument_pool(size: int = 1 << 24, seed: int = 5):
 
 
 def run_poisson(server: Server, requests, pool, keep=None, on_done=None):
-    """Submit requests [(t_arrival, length, n_max, precision 0/1)] at their arrival times.
+    """Submit requests [(t_arrival, length, n_max, precision class)] at their arrival times.
 
     Each request's arguments are a window of `pool` (starting at a request-specific
     offset).  Completed requests are released at once, except those whose index is in
@@ -162,7 +162,7 @@ def run_poisson(server: Server, requests, pool, keep=None, on_done=None):
         off = (i * 1000003) % (P - ln)
         now = time.perf_counter() - t0
         lag.append(now - ta)
-        rid = server.submit(pool[off:off + ln], nm, "fp64" if pr == 0 else "fp32")
+        rid = server.submit(pool[off:off + ln], nm, pr)
         if first_submit is None:
             first_submit = now
         id2idx[rid] = i
