@@ -38,10 +38,11 @@ sys.path.insert(0, REPO)
 
 N_ARGS = 1 << 26
 N_MAX = 16
+SPLIT_NBAR = 8   # the two-approximation option: rows 0..8 from the order-8 approximant
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(REPO, "profiles", "traffic_boys_f64_n16.json")
 KERNEL_SOURCES = [os.path.join(REPO, "paper_2504_07637_amd", "csrc", f)
-                  for f in ("boys_device.h", "boys_lib.hip", "boys_tables.inc")]
+                  for f in ("boys_device.h", "boys_kernels.h", "plain_inst.hip", "boys_tables.inc")]
 
 
 def kernel_hash() -> str:
@@ -110,8 +111,11 @@ def accuracy(torch, boys, xd, x):
     ti = torch.from_numpy(idx).to(xd.device)
     out = {}
     hi, lo = orc.exact(x[idx], N_MAX)
-    for prec in ("fp64", "fp32", "fp32x"):
-        F = boys.boys_eval(xd, N_MAX, prec)[:, ti].double().cpu().numpy()
+    for prec in ("fp64", "fp32", "fp32x", "fp64_split8"):
+        if prec == "fp64_split8":
+            F = boys.boys_eval_split(xd, N_MAX, SPLIT_NBAR)[:, ti].cpu().numpy()
+        else:
+            F = boys.boys_eval(xd, N_MAX, prec)[:, ti].double().cpu().numpy()
         per_m = []
         for m in range(N_MAX + 1):
             ok = np.abs(hi[m]) >= 1.1754943508222875e-38
@@ -224,6 +228,8 @@ def main():
                           args.steps, args.warmup)
     wall32x, gpu32x = timed(torch, lambda: boys.boys_eval(xd, N_MAX, "fp32x", out=out32),
                             args.steps, args.warmup)
+    wall_sp, gpu_sp = timed(torch, lambda: boys.boys_eval_split(xd, N_MAX, SPLIT_NBAR, out=out64),
+                            args.steps, args.warmup)
     values = (N_MAX + 1) * N_ARGS
     ms64 = wall64 / args.steps * 1e3
     v64 = values * args.steps / wall64
@@ -257,6 +263,10 @@ def main():
                  "speedup_vs_fp64": v32 / v64,
                  "launch_ms": gpu32 / args.steps * 1e3,
                  "hbm_GBs": (8 + 4 * (N_MAX + 1)) * N_ARGS / (gpu32 / args.steps) / 1e9},
+        "fp64_split8": {"value": values * args.steps / wall_sp, "unit": "values/s",
+                        "n_bar": SPLIT_NBAR, "ms_per_step": wall_sp / args.steps * 1e3,
+                        "launch_ms": gpu_sp / args.steps * 1e3,
+                        "hbm_GBs": alg_bytes / (gpu_sp / args.steps) / 1e9},
         "fp32x": {"value": values * args.steps / wall32x, "unit": "values/s",
                   "ms_per_step": wall32x / args.steps * 1e3,
                   "speedup_vs_fp64": wall64 / wall32x,

@@ -83,6 +83,19 @@ typedef enum {
 boys_status boys_eval(const double *x, int64_t n, int32_t n_max, void *out, int64_t ld_out,
                       int32_t precision, void *stream);
 
+/*
+ * The two-approximation option of section "Computations", binary64: when the highest
+ * accuracy is wanted for the orders m = 0..n_bar, F_{n_bar} and F_{n_max} are both taken
+ * from their own best approximants (cut-offs z_{n_bar,53} and z_{n_max,53}) and two
+ * downward recursions of Eq. r run, from n_max to n_bar+1 and from n_bar to 0, with one
+ * exp(-x).  Rows 0..n_bar equal boys_eval(..., n_bar, BOYS_FP64) bit for bit and rows
+ * n_bar+1..n_max equal those of boys_eval(..., n_max, BOYS_FP64).  Output binary64, layout
+ * and conventions as boys_eval.  Requires 0 <= n_bar < n_max <= boys_max_nmax(BOYS_FP64)
+ * (BOYS_ERR_UNSUPPORTED_NMAX otherwise).
+ */
+boys_status boys_eval_split(const double *x, int64_t n, int32_t n_bar, int32_t n_max, void *out,
+                            int64_t ld_out, void *stream);
+
 /* One argument array of a batch (host struct; x and out are device pointers). */
 typedef struct {
     const double *x;
@@ -98,7 +111,7 @@ typedef struct {
  * schedule 0: persistent workgroups (grid_per_cu per compute unit) take tiles from a work
  *             counter in table order;
  * schedule 1: one workgroup per tile, dispatched by the hardware in table order;
- *             tile must be block x 1, 2, 4 or 8.
+ *             tile must be block x 1, 2 or 4.
  */
 typedef struct {
     int32_t tile;        /* arguments per tile, a multiple of the block size */
@@ -167,7 +180,7 @@ typedef struct {
     int64_t budget_bytes; /* device memory for admitted requests (inputs + outputs) */
     int32_t streams;      /* execution slots, one HIP stream each (0 = 4) */
     int32_t max_batch;    /* requests per launch (0 = 256) */
-    int32_t tile;         /* arguments per tile: 256, 512, 1024 or 2048 (0 = 256); one
+    int32_t tile;         /* arguments per tile: 256, 512 or 1024 (0 = 256); one
                              256-thread workgroup per tile */
     int32_t max_tiles;    /* tiles per launch (0 = 65536); larger requests are refused */
 } boys_server_config;

@@ -15,6 +15,8 @@ approx_f64(x, n)          the binary64 approximant (Eqs. fq, pqz, pz, qz, r, lim
 approx_mixed(x, n)        the mixed binary32/binary64 class, shape (n+1, len(x)), float32.
 approx_f32x(x, n)         the binary32-output class computed in binary64 (the ~28-bit
                           approximant, each value rounded once), shape (n+1, len(x)), float32.
+approx_split(x, n, nbar)  the two-approximation option: rows 0..nbar of approx_f64(x, nbar)
+                          over rows nbar+1..n of approx_f64(x, n).
 approx_exact_n(x, n)      F~_n in binary128 from the 40-digit coefficients, as (hi, lo).
 exp_neg(x)                correctly rounded exp(-x) as both approximants use it.
 load_dataset(path)        the parsed coefficient dataset.
@@ -255,6 +257,16 @@ def approx_f32x(x, n: int, rec: Record | None = None):
     record's own cut-off), each value rounded to nearest binary32 once at the end."""
     r = rec if rec is not None else record("fp32x", n)
     return approx_f64(x, n, r).astype(np.float32)
+
+
+def approx_split(x, n: int, nbar: int):
+    """The two-approximation option of section "Computations": F_0..F_nbar as the
+    order-nbar evaluation gives them, F_{nbar+1}..F_n as the order-n evaluation does."""
+    if not 0 <= nbar < n:
+        raise ValueError("need 0 <= nbar < n")
+    lo = approx_f64(x, nbar)
+    hi = approx_f64(x, n)
+    return np.concatenate([lo, hi[nbar + 1:]], axis=0)
 
 
 def approx_exact_n(x, n: int, cls: str = "fp64", fields=None):

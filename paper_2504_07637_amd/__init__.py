@@ -16,7 +16,7 @@ import ctypes
 from . import _lib
 from ._lib import FP32, FP32X, FP64, FP64_PLUS, BoysArray, BoysError, BoysTuning
 
-__all__ = ["boys_eval", "boys_eval_batched", "Plan", "autotune", "max_nmax", "cutoff",
+__all__ = ["boys_eval", "boys_eval_split", "boys_eval_batched", "Plan", "autotune", "max_nmax", "cutoff",
            "precision_code", "padded_ld", "empty_out", "BoysError", "FP64", "FP32", "FP64_PLUS",
            "FP32X"]
 
@@ -97,6 +97,26 @@ def boys_eval(x, n_max: int, precision="fp64", out=None, stream=None):
                                   ctypes.c_void_p(out.data_ptr()), ld, code,
                                   _stream_ptr(stream, x.device))
     _lib.check(st, "boys_eval")
+    return out
+
+
+def boys_eval_split(x, n_max: int, n_bar: int, out=None, stream=None):
+    """The two-approximation option (binary64): rows 0..n_bar from the order-n_bar
+    approximant and its recursion, rows n_bar+1..n_max from the order-n_max one."""
+    torch = _torch()
+    _check_x(x)
+    n = x.numel()
+    if out is None:
+        out = empty_out(n, n_max, FP64, x.device)
+    elif (out.dtype != torch.float64 or out.device != x.device or out.dim() != 2
+          or out.shape[0] != n_max + 1 or out.shape[1] != n or out.stride(1) != 1):
+        raise ValueError("out must be a float64 (n_max+1, n) tensor with unit column stride")
+    ld = out.stride(0) if n > 0 else 1
+    with torch.cuda.device(x.device):
+        st = _lib.lib().boys_eval_split(ctypes.c_void_p(x.data_ptr()), n, n_bar, n_max,
+                                        ctypes.c_void_p(out.data_ptr()), ld,
+                                        _stream_ptr(stream, x.device))
+    _lib.check(st, "boys_eval_split")
     return out
 
 

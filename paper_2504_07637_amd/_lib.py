@@ -25,6 +25,7 @@ ERR_DEVICE = 4
 # every function declared in include/boys.h
 EXPORTS = (
     "boys_eval",
+    "boys_eval_split",
     "boys_eval_batched",
     "boys_plan_create",
     "boys_plan_update",
@@ -91,6 +92,8 @@ def lib():
         vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
         L.boys_eval.argtypes = [vp, i64, i32, vp, i64, i32, vp]
         L.boys_eval.restype = ctypes.c_int
+        L.boys_eval_split.argtypes = [vp, i64, i32, i32, vp, i64, vp]
+        L.boys_eval_split.restype = ctypes.c_int
         L.boys_eval_batched.argtypes = [ctypes.POINTER(BoysArray), i32, vp]
         L.boys_eval_batched.restype = ctypes.c_int
         L.boys_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(BoysArray), i32,

@@ -2,12 +2,17 @@
 
     python -m paper_2504_07637_amd.build
 
-Steps: regenerate csrc/boys_tables.inc from data/boys_coeffs.txt, then one hipcc call
-that compiles csrc/boys_lib.hip (kernels, plans) and csrc/boys_serve.hip (serving loop)
-into paper_2504_07637_amd/libboys.so.
+Steps: regenerate csrc/boys_tables.inc from data/boys_coeffs.txt; compile, in parallel,
+the host side (csrc/boys_lib.hip), the serving loop (csrc/boys_serve.hip), the plain
+kernels once per precision class (csrc/plain_inst.hip) and the batched kernels once per
+(n_max bucket, launch shape) (csrc/batched_inst.hip), and the two-approximation
+kernels (csrc/split_inst.hip) into objects under _build/; link
+them into paper_2504_07637_amd/libboys.so.  BOYS_BUILD_JOBS caps the parallel compiles
+(default: the CPU count, at most 16).
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import os
 import shutil
 import subprocess
@@ -18,6 +23,11 @@ REPO = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(REPO, "include")
 LIB = os.path.join(PKG, "libboys.so")
+BUILD_DIR = os.path.join(PKG, "_build")
+
+CLASSES = (0, 1, 2, 3)          # boys_precision values
+BUCKETS = 5                     # n_max buckets of the batched kernels
+SHAPES = (0, 1, 2, 4)           # 0: persistent; K: one workgroup per tile of K * block
 ARCH = os.environ.get("BOYS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -25,7 +35,6 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # every + - * / sqrt stays one IEEE operation; fmas only where written
     "-ffp-contract=off",
     # no packed FP32 instructions
@@ -51,11 +60,50 @@ def gen_tables() -> str:
     return gen_tables.main()
 
 
+def _units():
+    """(object name, source, extra flags) of every translation unit."""
+    # the largest kernels (high buckets, large K) take longest: start them first
+    units = [(f"batched_b{b}_k{k}", "batched_inst.hip", [f"-DBOYS_BUCKET={b}", f"-DBOYS_K={k}"])
+             for b in reversed(range(BUCKETS)) for k in sorted(SHAPES, reverse=True)]
+    units += [(f"plain_c{c}", "plain_inst.hip", [f"-DBOYS_CLASS={c}"]) for c in CLASSES]
+    units += [("split", "split_inst.hip", [])]
+    units += [("boys_lib", "boys_lib.hip", []), ("boys_serve", "boys_serve.hip", [])]
+    return units
+
+
+def _jobs() -> int:
+    env = os.environ.get("BOYS_BUILD_JOBS")
+    if env:
+        return max(1, int(env))
+    return max(1, min(os.cpu_count() or 1, 16))
+
+
 def build_lib(verbose: bool = False) -> str:
     gen_tables()
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    cc = hipcc()
+    base = [cc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC]
+
+    def compile_one(unit):
+        name, src, extra = unit
+        obj = os.path.join(BUILD_DIR, name + ".o")
+        cmd = [*base, *extra, "-c", "-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+        return obj, cmd, r.returncode, r.stdout
+
+    units = _units()
+    with cf.ThreadPoolExecutor(max_workers=_jobs()) as pool:
+        results = list(pool.map(compile_one, units))
+    failed = [(cmd, out) for _, cmd, rc, out in results if rc != 0]
+    for cmd, out in failed:
+        sys.stderr.write(" ".join(cmd) + "\n" + out + "\n")
+    if failed:
+        raise RuntimeError(f"{len(failed)} of {len(units)} HIP compiles failed")
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-o", tmp,
-           os.path.join(CSRC, "boys_lib.hip"), os.path.join(CSRC, "boys_serve.hip"), "-lpthread"]
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
+           *[obj for obj, _, _, _ in results], "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -1,0 +1,34 @@
+// batched_inst.hip -- one batched kernel and its launcher: n_max bucket B (the largest
+// order it dispatches is kBuckets[B]) and launch shape K (0: persistent workgroups with a
+// work counter; 1, 2, 4: one workgroup per tile of K * blockDim arguments).
+// Compiled once per (B, K) with -DBOYS_BUCKET=<B> -DBOYS_K=<K>.
+#include <algorithm>
+
+#include "boys_kernels.h"
+
+#if !defined(BOYS_BUCKET) || !defined(BOYS_K)
+#error "compile with -DBOYS_BUCKET=<bucket> -DBOYS_K=<0, 1, 2 or 4>"
+#endif
+
+template <int B, int K>
+hipError_t boys_internal::launch_bucket(const Desc *d_desc, const int2 *d_tiles, int32_t ntiles,
+                                        uint32_t *d_counter, const Launch &L, hipStream_t s)
+{
+    static_assert(B >= 0 && B < kNumBuckets, "bucket out of range");
+    constexpr int kMax = kBuckets[B];
+    if constexpr (K == 0) {
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, d_counter);
+        if (ntiles > 0)
+            hipLaunchKernelGGL((k_batched<kMax>), dim3(std::max(1, std::min(L.grid, ntiles))),
+                               dim3(L.block), 0, s, d_desc, d_tiles, ntiles, L.tile, d_counter);
+    } else {
+        static_assert(K == 1 || K == 2 || K == 4, "unsupported tile factor");
+        if (ntiles > 0)
+            hipLaunchKernelGGL((k_batched_wg<kMax, K>), dim3(ntiles), dim3(L.block), 0, s,
+                               d_desc, d_tiles, L.tile);
+    }
+    return hipGetLastError();
+}
+
+template hipError_t boys_internal::launch_bucket<BOYS_BUCKET, BOYS_K>(
+    const Desc *, const int2 *, int32_t, uint32_t *, const Launch &, hipStream_t);

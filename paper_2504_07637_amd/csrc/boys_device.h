@@ -304,6 +304,132 @@ __host__ __device__ __forceinline__ void eval_f32r(double x, const double2 *__re
 }
 
 // ---------------------------------------------------------------------------------
+// The two-approximation option of section "Computations" (binary64): F_nbar and F_N from
+// their own best approximants (order nbar given at run time, nbar < N), the downward
+// recursion from N to nbar+1 and from nbar to 0, one exp(-x) for both.  Every value is
+// the one the plain evaluation of its own order gives: rows 0..nbar those of order nbar,
+// rows nbar+1..N those of order N.
+
+// factors() for a set read at run time: the same operations in the same order
+__host__ __device__ __forceinline__ double factors_rt(double x, const double *c, int ng, int nq,
+                                                      int nl)
+{
+    double p = 1.0;
+    for (int k = ng - 1; k >= 0; --k)
+        p = p * x + c[k];
+    c += ng;
+    for (int k = 0; k < nq; ++k)
+        p = p * ((x - c[2 * k]) * (x - c[2 * k]) + c[2 * k + 1]);
+    c += 2 * nq;
+    for (int k = 0; k < nl; ++k)
+        p = p * (x - c[k]);
+    return p;
+}
+
+// powi<K>() for a run-time K >= 0: the same left-to-right binary powering
+__host__ __device__ __forceinline__ double powi_rt(double y, int k)
+{
+    if (k == 0)
+        return 1.0;
+    const int top = 31 - __builtin_clz((unsigned)k);
+    double r = y;
+    for (int b = top - 1; b >= 0; --b) {
+        r = r * r;
+        if ((k >> b) & 1)
+            r = r * y;
+    }
+    return r;
+}
+
+// F[M-1] .. F[nbar+1] by Eq. r from f = F[M] (steps at or below nbar skipped)
+template <int M>
+__host__ __device__ __forceinline__ void recurse_down_to(int nbar, double x2, double e, double f,
+                                                         double *F)
+{
+    if constexpr (M >= 1) {
+        if (M - 1 > nbar) {
+            const double g = div_odd<M>(x2 * f + e);
+            F[M - 1] = g;
+            recurse_down_to<M - 1>(nbar, x2, e, g, F);
+        }
+    }
+}
+
+// F[M] for M = nbar..0 by Eq. r, starting from g = F[nbar]; M runs down from a
+// compile-time bound so that every divisor is a constant
+template <int M>
+__host__ __device__ __forceinline__ void recurse_low(int nbar, double x2, double e, double &g,
+                                                     double *F)
+{
+    if (M <= nbar) {
+        if (M < nbar)
+            g = div_odd<M + 1>(x2 * g + e);
+        F[M] = g;
+    }
+    if constexpr (M > 0)
+        recurse_low<M - 1>(nbar, x2, e, g, F);
+}
+
+// the upward product of Eq. limf1 for F[1..lim] from f = F[0]
+template <int N>
+__host__ __device__ __forceinline__ void chain_up(int lim, double ix, double f, double *F)
+{
+#pragma unroll
+    for (int m = 1; m <= N; ++m) {
+        if (m <= lim) {
+            f = f * (m - 0.5) * ix;
+            F[m] = f;
+        }
+    }
+}
+
+template <int N>
+__host__ __device__ __forceinline__ void eval_split(double x, int nbar,
+                                                    const double2 *__restrict__ tab,
+                                                    double (&F)[N + 1])
+{
+    static_assert(N >= 1, "the two-approximation option needs nbar < N");
+    using S = boys_tab::F64Set<N>;
+    const boys_tab::RtSet &B = boys_tab::kRt64[nbar];
+    const bool below_n = !(x > S::z);  // z_nbar < z_N: below_b implies below_n
+    const bool below_b = !(x > B.z);
+    if (below_n) {
+        const double e = exp_rn(__builtin_fmax(-x, -120.0), tab);
+        const double u = factors<double, S::ug_n, S::uq_n, S::ul_n>(x, S::ug, S::uq, S::ul);
+        const double v = factors<double, S::vg_n, S::vq_n, S::vl_n>(x, S::vg, S::vq, S::vl);
+        const double Q = S::q0 + S::q1 * x + S::q2 * (u / v) * x * x;
+        const double W = powi<N>(Q) * __builtin_sqrt(Q) * e;
+        const double G = x + W;
+        const double f = S::c / (powi<N>(G) * __builtin_sqrt(G));
+        F[N] = f;
+        recurse_down_to<N>(nbar, 2.0 * x, e, f, F);
+        if (below_b) {
+            const double *cu = boys_tab::kRtCoef64 + B.off;
+            const double *cv = cu + B.ug_n + 2 * B.uq_n + B.ul_n;
+            const double ub = factors_rt(x, cu, B.ug_n, B.uq_n, B.ul_n);
+            const double vb = factors_rt(x, cv, B.vg_n, B.vq_n, B.vl_n);
+            const double Qb = B.q0 + B.q1 * x + B.q2 * (ub / vb) * x * x;
+            const double Wb = powi_rt(Qb, nbar) * __builtin_sqrt(Qb) * e;
+            const double Gb = x + Wb;
+            double g = B.c / (powi_rt(Gb, nbar) * __builtin_sqrt(Gb));
+            recurse_low<N - 1>(nbar, 2.0 * x, e, g, F);
+        }
+    }
+    if (!below_b) {
+        // Eq. limf1 for rows 0..nbar (z_nbar < x <= z_N) or for every row (x > z_N)
+        const double ix = 1.0 / x;
+        const double f = boys_tab::kC0 / __builtin_sqrt(x);
+        F[0] = f;
+        chain_up<N>(below_n ? nbar : N, ix, f, F);
+    }
+    if (!(x >= 0.0)) {
+#pragma unroll
+        for (int m = 0; m <= N; ++m)
+            F[m] = __builtin_nan("");
+    }
+}
+
+// ---------------------------------------------------------------------------------
 // F_0..F_N for one argument, mixed binary32/binary64 class
 
 template <int N>

@@ -1,5 +1,6 @@
-// boys_internal.h -- library-internal interface between the kernels (boys_lib.hip) and
-// the serving executor (boys_serve.hip).  Not part of the C ABI.
+// boys_internal.h -- library-internal interface between the kernel instantiation units
+// (plain_inst.hip, batched_inst.hip, split_inst.hip), the host side (boys_lib.hip) and the serving
+// executor (boys_serve.hip).  Not part of the C ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -33,5 +34,25 @@ hipError_t launch_batched(const Desc *d_desc, const int2 *d_tiles, int32_t ntile
                           uint32_t *d_counter, int maxn, const Launch &L, hipStream_t s);
 
 int cu_count();
+
+// the plain launch of precision class C at order n (nullptr outside 0..the class's largest
+// order); defined per class in plain_inst.hip
+using PlainLaunch = hipError_t (*)(const double *x, int64_t n, void *out, int64_t ld,
+                                   hipStream_t s);
+template <int C>
+PlainLaunch plain_launcher(int n);
+
+// the two-approximation launch at order n (1..the binary64 maximum; nullptr otherwise);
+// defined in split_inst.hip
+using SplitLaunch = hipError_t (*)(const double *x, int64_t n, double *out, int64_t ld,
+                                   int nbar, hipStream_t s);
+SplitLaunch split_launcher(int n);
+
+// the batched kernel of n_max bucket B with launch shape K (0: persistent, [zero the
+// counter, kernel]; 1, 2, 4, 8: one workgroup per tile of K * L.block arguments); defined
+// per (B, K) in batched_inst.hip
+template <int B, int K>
+hipError_t launch_bucket(const Desc *d_desc, const int2 *d_tiles, int32_t ntiles,
+                         uint32_t *d_counter, const Launch &L, hipStream_t s);
 
 }  // namespace boys_internal

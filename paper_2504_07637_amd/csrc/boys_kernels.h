@@ -1,0 +1,317 @@
+// boys_kernels.h -- the device code of libboys.so: per-argument bodies and kernels.
+//
+// Included by the instantiation units (plain_inst.hip: the plain kernels of one precision
+// class; batched_inst.hip: the batched kernels of one n_max bucket and one launch shape),
+// which the build compiles in parallel.  Everything here has internal linkage, so each
+// unit holds only the kernels it instantiates.
+//
+// Kernels (gfx950, wave64):
+//   k_plain<C, N>    one lane per argument, one argument per lane (a full grid: for the
+//                    (n_max+1)-row output this launch shape keeps the HBM write streams
+//                    densest); x is read and the output rows are written with coalesced
+//                    non-temporal accesses (for a wave, 512 contiguous bytes per binary64
+//                    row).  The binary64-output classes read the 4 KiB exp table through
+//                    the L1 cache with 128-thread workgroups; the binary32-output classes
+//                    stage it in LDS with 512-thread workgroups (the faster shape for each,
+//                    by measurement).
+//   k_batched<MAXN>  persistent workgroups pull tiles from a device counter; a tile is
+//                    one slice of one array, so (precision, n_max) is uniform per tile and
+//                    the per-tile dispatch is a scalar branch to the same unrolled bodies
+//                    that k_plain uses, which makes batched results equal to solo ones
+//                    bit for bit.
+//   k_batched_wg<MAXN, K>  one workgroup per tile of K * blockDim arguments.
+//   k_split<N>       the two-approximation option (binary64, lower order a launch argument),
+//                    shaped as k_plain.
+//   k_reset          zeroes the tile counter (a kernel rather than a memset node, so the
+//                    plan's graph replays correctly).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "boys.h"
+#include "boys_device.h"
+#include "boys_internal.h"
+
+namespace {
+
+using boys_tab::kMaxN32;
+using boys_tab::kMaxN32x;
+using boys_tab::kMaxN64;
+
+constexpr int kMaxN = kMaxN64 > kMaxN32 ? (kMaxN64 > kMaxN32x ? kMaxN64 : kMaxN32x)
+                                        : (kMaxN32 > kMaxN32x ? kMaxN32 : kMaxN32x);
+
+// n_max buckets of the batched kernels: a batch runs the smallest MAXN >= its largest n_max
+constexpr int kBuckets[] = {4, 8, 16, 24, kMaxN};
+constexpr int kNumBuckets = 5;
+
+using boys_internal::Desc;
+
+
+using boys_internal::Desc;
+
+__device__ __forceinline__ void load_exp_table(double2 *tab)
+{
+    for (int t = threadIdx.x; t < 256; t += blockDim.x)
+        tab[t] = make_double2(boys_tab::kExp2Tab[2 * t], boys_tab::kExp2Tab[2 * t + 1]);
+    __syncthreads();
+}
+
+template <int N>
+__device__ __forceinline__ void body_f64(const double *__restrict__ x, double *__restrict__ out,
+                                         int64_t ld, int64_t i, const double2 *tab)
+{
+    double F[N + 1];
+    boys::eval_f64<N>(__builtin_nontemporal_load(x + i), tab, F);
+#pragma unroll
+    for (int m = 0; m <= N; ++m)
+        __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
+}
+
+// binary64, F_0..F_N from the order N+1 approximant and one more recursion step
+template <int N>
+__device__ __forceinline__ void body_f64plus(const double *__restrict__ x,
+                                             double *__restrict__ out, int64_t ld, int64_t i,
+                                             const double2 *tab)
+{
+    double F[N + 2];
+    boys::eval_f64<N + 1>(__builtin_nontemporal_load(x + i), tab, F);
+#pragma unroll
+    for (int m = 0; m <= N; ++m)
+        __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
+}
+
+// binary32 output from binary64 arithmetic with the ~28-bit approximants; each value is
+// rounded once to binary32 at the store
+template <int N>
+__device__ __forceinline__ void body_f32x(const double *__restrict__ x, float *__restrict__ out,
+                                          int64_t ld, int64_t i, const double2 *tab)
+{
+    double F[N + 1];
+    boys::eval_f32r<N>(__builtin_nontemporal_load(x + i), tab, F);
+#pragma unroll
+    for (int m = 0; m <= N; ++m)
+        __builtin_nontemporal_store((float)F[m], out + (int64_t)m * ld + i);
+}
+
+// one argument of class C (a boys_precision value) at order N
+template <int C, int N>
+__device__ __forceinline__ void body(const Desc &d, int64_t i, const double2 *tab);
+
+template <int N>
+__device__ __forceinline__ void body_f32(const double *__restrict__ x, float *__restrict__ out,
+                                         int64_t ld, int64_t i, const double2 *tab)
+{
+    float F[N + 1];
+    boys::eval_f32<N>(__builtin_nontemporal_load(x + i), tab, F);
+#pragma unroll
+    for (int m = 0; m <= N; ++m)
+        __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
+}
+
+constexpr int cmin(int a, int b)
+{
+    return a < b ? a : b;
+}
+
+// block size of the plain kernel per class
+template <int C>
+constexpr int plain_block()
+{
+    return C == BOYS_FP32 || C == BOYS_FP32X ? 512 : 128;
+}
+
+// largest order of a class
+template <int C>
+constexpr int class_max()
+{
+    return C == BOYS_FP32 ? kMaxN32 : C == BOYS_FP64 ? kMaxN64 : C == BOYS_FP32X ? kMaxN32x
+                                                                            : kMaxN64 - 1;
+}
+
+template <int C, int N>
+__device__ __forceinline__ void body(const Desc &d, int64_t i, const double2 *tab)
+{
+    if constexpr (C == BOYS_FP64)
+        body_f64<N>(d.x, static_cast<double *>(d.out), d.ld, i, tab);
+    else if constexpr (C == BOYS_FP64_PLUS)
+        body_f64plus<N>(d.x, static_cast<double *>(d.out), d.ld, i, tab);
+    else if constexpr (C == BOYS_FP32X)
+        body_f32x<N>(d.x, static_cast<float *>(d.out), d.ld, i, tab);
+    else
+        body_f32<N>(d.x, static_cast<float *>(d.out), d.ld, i, tab);
+}
+
+template <int C, int N>
+__global__ __launch_bounds__(plain_block<C>()) void k_plain(const double *__restrict__ x, int64_t n,
+                                                            void *__restrict__ out, int64_t ld)
+{
+    constexpr int BS = plain_block<C>();
+    const double2 *tab;
+    if constexpr (C != BOYS_FP32 && C != BOYS_FP32X) {
+        tab = reinterpret_cast<const double2 *>(boys_tab::kExp2Tab);
+    } else {
+        __shared__ double2 lds_tab[256];
+        load_exp_table(lds_tab);
+        tab = lds_tab;
+    }
+    // one argument per lane and no loop: a grid-stride loop, even one that runs once,
+    // costs about 10% here (measured); the host splits arrays too long for one grid
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (i < n) {
+        if constexpr (C == BOYS_FP64)
+            body_f64<N>(x, static_cast<double *>(out), ld, i, tab);
+        else if constexpr (C == BOYS_FP64_PLUS)
+            body_f64plus<N>(x, static_cast<double *>(out), ld, i, tab);
+        else if constexpr (C == BOYS_FP32X)
+            body_f32x<N>(x, static_cast<float *>(out), ld, i, tab);
+        else
+            body_f32<N>(x, static_cast<float *>(out), ld, i, tab);
+    }
+}
+
+// The batched kernels inline all 4 x 37 (class, order) bodies, times the unroll factor K.
+// Calling them as functions instead (once per tile) cut the compile time but cost
+// occupancy and scratch (callee-saved registers, no occupancy target in the callees),
+// so they stay inlined and the build compiles each (bucket, K) kernel in a unit of its
+// own, in parallel.
+
+// the exp table as the bodies of class C read it: binary64 classes from global memory
+// through L1, the mixed class from the LDS copy that the kernel stages in s_exp_tab
+__shared__ double2 s_exp_tab[256];
+
+template <int C>
+__device__ __forceinline__ const double2 *exp_tab()
+{
+    if constexpr (C == BOYS_FP32)
+        return s_exp_tab;
+    else
+        return reinterpret_cast<const double2 *>(boys_tab::kExp2Tab);
+}
+
+// arguments [start, start + cnt) of one array, blockDim-strided
+template <int C, int N>
+__device__ __forceinline__ void tile_strided(const double *x, void *out, int64_t ld, int64_t start,
+                                          int64_t cnt)
+{
+    const Desc d{x, out, start + cnt, ld, N, C};
+    const double2 *tab = exp_tab<C>();
+    for (int64_t j = threadIdx.x; j < cnt; j += blockDim.x)
+        body<C, N>(d, start + j, tab);
+}
+
+// K guarded iterations, fully unrolled (no loop): a tile of K * blockDim arguments
+template <int C, int N, int K>
+__device__ __forceinline__ void tile_unrolled(const double *x, void *out, int64_t n, int64_t ld,
+                                           int64_t start)
+{
+    const Desc d{x, out, n, ld, N, C};
+    const double2 *tab = exp_tab<C>();
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        const int64_t i = start + (int64_t)a * blockDim.x + threadIdx.x;
+        if (i < n)
+            body<C, N>(d, i, tab);
+    }
+}
+
+// scalar dispatch over n (wave-uniform) to the tile functions of orders N, N-1, ..., 0;
+// K == 0 selects the strided form
+template <int C, int N, int K>
+__device__ __forceinline__ void dispatch(int n, const Desc &d, int64_t start, int64_t cnt)
+{
+    if (n == N) {
+        if constexpr (K == 0)
+            tile_strided<C, N>(d.x, d.out, d.ld, start, cnt);
+        else
+            tile_unrolled<C, N, K>(d.x, d.out, d.n, d.ld, start);
+    } else if constexpr (N > 0) {
+        dispatch<C, N - 1, K>(n, d, start, cnt);
+    }
+}
+
+template <int MAXN, int K>
+__device__ __forceinline__ void dispatch_class(int prec, int n, const Desc &d, int64_t start,
+                                               int64_t cnt)
+{
+    if (prec == BOYS_FP64)
+        dispatch<BOYS_FP64, cmin(MAXN, class_max<BOYS_FP64>()), K>(n, d, start, cnt);
+    else if (prec == BOYS_FP32)
+        dispatch<BOYS_FP32, cmin(MAXN, class_max<BOYS_FP32>()), K>(n, d, start, cnt);
+    else if (prec == BOYS_FP32X)
+        dispatch<BOYS_FP32X, cmin(MAXN, class_max<BOYS_FP32X>()), K>(n, d, start, cnt);
+    else
+        dispatch<BOYS_FP64_PLUS, cmin(MAXN, class_max<BOYS_FP64_PLUS>()), K>(n, d, start, cnt);
+}
+
+template <int MAXN>
+__global__ __launch_bounds__(256) void k_batched(const Desc *__restrict__ descs,
+                                                 const int2 *__restrict__ tiles,
+                                                 int32_t ntiles, int32_t tile_args,
+                                                 uint32_t *__restrict__ counter)
+{
+    __shared__ int32_t s_tile;
+    load_exp_table(s_exp_tab);
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_tile = (int32_t)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int32_t t = __builtin_amdgcn_readfirstlane(s_tile);
+        __syncthreads();
+        if (t >= ntiles)
+            break;
+        const int2 ts = tiles[t];
+        const int32_t a = __builtin_amdgcn_readfirstlane(ts.x);
+        const Desc d = descs[a];
+        const int64_t start = (int64_t)__builtin_amdgcn_readfirstlane(ts.y) * tile_args;
+        const int64_t rem = d.n - start;
+        const int64_t cnt = rem < tile_args ? rem : tile_args;
+        dispatch_class<MAXN, 0>(__builtin_amdgcn_readfirstlane(d.prec),
+                                __builtin_amdgcn_readfirstlane(d.n_max), d, start, cnt);
+    }
+}
+
+// one workgroup per tile: the hardware dispatcher hands out the tiles in table order
+// (longest first), no work counter; binary64 bodies read the exp table through L1,
+// binary32 bodies stage it in LDS, as the plain kernels do
+template <int MAXN, int K>
+__global__ __launch_bounds__(256) void k_batched_wg(const Desc *__restrict__ descs,
+                                                    const int2 *__restrict__ tiles,
+                                                    int32_t tile_args)
+{
+    const int2 ts = tiles[blockIdx.x];
+    const int32_t a = __builtin_amdgcn_readfirstlane(ts.x);
+    const Desc d = descs[a];
+    const int64_t start = (int64_t)__builtin_amdgcn_readfirstlane(ts.y) * tile_args;
+    const int prec = __builtin_amdgcn_readfirstlane(d.prec);
+    if (prec == BOYS_FP32)
+        load_exp_table(s_exp_tab);
+    dispatch_class<MAXN, K>(prec, __builtin_amdgcn_readfirstlane(d.n_max), d, start, 0);
+}
+
+// the two-approximation option (binary64): one lane per argument, as k_plain<BOYS_FP64, N>;
+// nbar is wave-uniform (a kernel argument)
+template <int N>
+__global__ __launch_bounds__(128) void k_split(const double *__restrict__ x, int64_t n,
+                                               double *__restrict__ out, int64_t ld, int nbar)
+{
+    const int64_t i = (int64_t)blockIdx.x * 128 + threadIdx.x;
+    if (i < n) {
+        double F[N + 1];
+        boys::eval_split<N>(__builtin_nontemporal_load(x + i), nbar,
+                            reinterpret_cast<const double2 *>(boys_tab::kExp2Tab), F);
+#pragma unroll
+        for (int m = 0; m <= N; ++m)
+            __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
+    }
+}
+
+__global__ void k_reset(uint32_t *counter)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *counter = 0u;
+}
+
+}  // namespace

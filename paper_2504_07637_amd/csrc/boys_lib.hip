@@ -1,20 +1,7 @@
-// boys_lib.hip -- kernels and C ABI of libboys.so (see include/boys.h).
-//
-// Kernels (gfx950, wave64):
-//   k_plain<C, N, BS> one lane per argument, one argument per lane (a full grid: for the
-//                    (n_max+1)-row output this launch shape keeps the HBM write streams
-//                    densest); x is read and the output rows are written with coalesced
-//                    non-temporal accesses (for a wave, 512 contiguous bytes per binary64
-//                    row).  The binary64 class reads the 4 KiB exp table through the L1
-//                    cache with 128-thread workgroups; the mixed class stages it in LDS
-//                    with 512-thread workgroups (the faster shape for each, by measurement).
-//   k_batched<MAXN>  persistent workgroups pull tiles from a device counter; a tile is
-//                    one slice of one array, so (precision, n_max) is uniform per tile and
-//                    the per-tile dispatch is a scalar branch to the same unrolled bodies
-//                    that k_plain uses, which makes batched results equal to solo ones
-//                    bit for bit.
-//   k_reset          zeroes the tile counter (a kernel rather than a memset node, so the
-//                    plan's graph replays correctly).
+// boys_lib.hip -- host side and C ABI of libboys.so (see include/boys.h): argument
+// checks, dispatch to the kernels (boys_kernels.h, instantiated in plain_inst.hip,
+// batched_inst.hip and split_inst.hip), batch schedules, plans with HIP graphs, the
+// autotuner.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,252 +21,17 @@
 
 namespace {
 
+using boys_internal::Desc;
 using boys_tab::kMaxN32;
-using boys_tab::kMaxN64;
 using boys_tab::kMaxN32x;
+using boys_tab::kMaxN64;
 
+// n_max buckets of the batched kernels (the same list as boys_kernels.h's kBuckets)
 constexpr int kMaxN = kMaxN64 > kMaxN32 ? (kMaxN64 > kMaxN32x ? kMaxN64 : kMaxN32x)
                                         : (kMaxN32 > kMaxN32x ? kMaxN32 : kMaxN32x);
+constexpr int kBuckets[] = {4, 8, 16, 24, kMaxN};
+constexpr int kNumBuckets = 5;
 
-// ---------------------------------------------------------------------------------
-// device code
-
-using boys_internal::Desc;
-
-__device__ __forceinline__ void load_exp_table(double2 *tab)
-{
-    for (int t = threadIdx.x; t < 256; t += blockDim.x)
-        tab[t] = make_double2(boys_tab::kExp2Tab[2 * t], boys_tab::kExp2Tab[2 * t + 1]);
-    __syncthreads();
-}
-
-template <int N>
-__device__ __forceinline__ void body_f64(const double *__restrict__ x, double *__restrict__ out,
-                                         int64_t ld, int64_t i, const double2 *tab)
-{
-    double F[N + 1];
-    boys::eval_f64<N>(__builtin_nontemporal_load(x + i), tab, F);
-#pragma unroll
-    for (int m = 0; m <= N; ++m)
-        __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
-}
-
-// binary64, F_0..F_N from the order N+1 approximant and one more recursion step
-template <int N>
-__device__ __forceinline__ void body_f64plus(const double *__restrict__ x,
-                                             double *__restrict__ out, int64_t ld, int64_t i,
-                                             const double2 *tab)
-{
-    double F[N + 2];
-    boys::eval_f64<N + 1>(__builtin_nontemporal_load(x + i), tab, F);
-#pragma unroll
-    for (int m = 0; m <= N; ++m)
-        __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
-}
-
-// binary32 output from binary64 arithmetic with the ~28-bit approximants; each value is
-// rounded once to binary32 at the store
-template <int N>
-__device__ __forceinline__ void body_f32x(const double *__restrict__ x, float *__restrict__ out,
-                                          int64_t ld, int64_t i, const double2 *tab)
-{
-    double F[N + 1];
-    boys::eval_f32r<N>(__builtin_nontemporal_load(x + i), tab, F);
-#pragma unroll
-    for (int m = 0; m <= N; ++m)
-        __builtin_nontemporal_store((float)F[m], out + (int64_t)m * ld + i);
-}
-
-// one argument of class C (a boys_precision value) at order N
-template <int C, int N>
-__device__ __forceinline__ void body(const Desc &d, int64_t i, const double2 *tab);
-
-template <int N>
-__device__ __forceinline__ void body_f32(const double *__restrict__ x, float *__restrict__ out,
-                                         int64_t ld, int64_t i, const double2 *tab)
-{
-    float F[N + 1];
-    boys::eval_f32<N>(__builtin_nontemporal_load(x + i), tab, F);
-#pragma unroll
-    for (int m = 0; m <= N; ++m)
-        __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
-}
-
-constexpr int cmin(int a, int b)
-{
-    return a < b ? a : b;
-}
-
-// block size of the plain kernel per class
-template <int C>
-constexpr int plain_block()
-{
-    return C == BOYS_FP32 ? 512 : 128;
-}
-
-// largest order of a class
-template <int C>
-constexpr int class_max()
-{
-    return C == BOYS_FP32 ? kMaxN32 : C == BOYS_FP64 ? kMaxN64 : C == BOYS_FP32X ? kMaxN32x
-                                                                            : kMaxN64 - 1;
-}
-
-template <int C, int N>
-__device__ __forceinline__ void body(const Desc &d, int64_t i, const double2 *tab)
-{
-    if constexpr (C == BOYS_FP64)
-        body_f64<N>(d.x, static_cast<double *>(d.out), d.ld, i, tab);
-    else if constexpr (C == BOYS_FP64_PLUS)
-        body_f64plus<N>(d.x, static_cast<double *>(d.out), d.ld, i, tab);
-    else if constexpr (C == BOYS_FP32X)
-        body_f32x<N>(d.x, static_cast<float *>(d.out), d.ld, i, tab);
-    else
-        body_f32<N>(d.x, static_cast<float *>(d.out), d.ld, i, tab);
-}
-
-template <int C, int N>
-__global__ __launch_bounds__(plain_block<C>()) void k_plain(const double *__restrict__ x, int64_t n,
-                                                            void *__restrict__ out, int64_t ld)
-{
-    constexpr int BS = plain_block<C>();
-    const double2 *tab;
-    if constexpr (C != BOYS_FP32) {
-        tab = reinterpret_cast<const double2 *>(boys_tab::kExp2Tab);
-    } else {
-        __shared__ double2 lds_tab[256];
-        load_exp_table(lds_tab);
-        tab = lds_tab;
-    }
-    // one argument per lane and no loop: a grid-stride loop, even one that runs once,
-    // costs about 10% here (measured); the host splits arrays too long for one grid
-    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-    if (i < n) {
-        if constexpr (C == BOYS_FP64)
-            body_f64<N>(x, static_cast<double *>(out), ld, i, tab);
-        else if constexpr (C == BOYS_FP64_PLUS)
-            body_f64plus<N>(x, static_cast<double *>(out), ld, i, tab);
-        else if constexpr (C == BOYS_FP32X)
-            body_f32x<N>(x, static_cast<float *>(out), ld, i, tab);
-        else
-            body_f32<N>(x, static_cast<float *>(out), ld, i, tab);
-    }
-}
-
-template <int C, int N>
-__device__ __forceinline__ void tile_body(const Desc &d, int64_t start, int64_t cnt,
-                                          const double2 *tab)
-{
-    for (int64_t j = threadIdx.x; j < cnt; j += blockDim.x)
-        body<C, N>(d, start + j, tab);
-}
-
-// scalar dispatch over n (wave-uniform) to the unrolled bodies N = 0..MAXN
-template <int C, int N>
-__device__ __forceinline__ void dispatch_n(int n, const Desc &d, int64_t start, int64_t cnt,
-                                           const double2 *tab)
-{
-    if (n == N) {
-        tile_body<C, N>(d, start, cnt, tab);
-    } else if constexpr (N > 0) {
-        dispatch_n<C, N - 1>(n, d, start, cnt, tab);
-    }
-}
-
-template <int MAXN>
-__global__ __launch_bounds__(256) void k_batched(const Desc *__restrict__ descs,
-                                                 const int2 *__restrict__ tiles,
-                                                 int32_t ntiles, int32_t tile_args,
-                                                 uint32_t *__restrict__ counter)
-{
-    __shared__ double2 tab[256];
-    __shared__ int32_t s_tile;
-    load_exp_table(tab);
-    for (;;) {
-        if (threadIdx.x == 0)
-            s_tile = (int32_t)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int32_t t = __builtin_amdgcn_readfirstlane(s_tile);
-        __syncthreads();
-        if (t >= ntiles)
-            break;
-        const int2 ts = tiles[t];
-        const int32_t a = __builtin_amdgcn_readfirstlane(ts.x);
-        const Desc d = descs[a];
-        const int64_t start = (int64_t)__builtin_amdgcn_readfirstlane(ts.y) * tile_args;
-        const int64_t rem = d.n - start;
-        const int64_t cnt = rem < tile_args ? rem : tile_args;
-        const int n = __builtin_amdgcn_readfirstlane(d.n_max);
-        const int prec = __builtin_amdgcn_readfirstlane(d.prec);
-        if (prec == BOYS_FP64)
-            dispatch_n<BOYS_FP64, cmin(MAXN, class_max<BOYS_FP64>())>(n, d, start, cnt, tab);
-        else if (prec == BOYS_FP32)
-            dispatch_n<BOYS_FP32, cmin(MAXN, class_max<BOYS_FP32>())>(n, d, start, cnt, tab);
-        else if (prec == BOYS_FP32X)
-            dispatch_n<BOYS_FP32X, cmin(MAXN, class_max<BOYS_FP32X>())>(n, d, start, cnt, tab);
-        else
-            dispatch_n<BOYS_FP64_PLUS, cmin(MAXN, class_max<BOYS_FP64_PLUS>())>(n, d, start, cnt,
-                                                                                 tab);
-    }
-}
-
-// K guarded iterations, fully unrolled (no loop): a tile of K * blockDim arguments
-template <int C, int N, int K>
-__device__ __forceinline__ void tile_body_unrolled(const Desc &d, int64_t start,
-                                                   const double2 *tab)
-{
-#pragma unroll
-    for (int a = 0; a < K; ++a) {
-        const int64_t i = start + (int64_t)a * blockDim.x + threadIdx.x;
-        if (i < d.n)
-            body<C, N>(d, i, tab);
-    }
-}
-
-template <int C, int N, int K>
-__device__ __forceinline__ void dispatch_wg(int n, const Desc &d, int64_t start,
-                                            const double2 *tab)
-{
-    if (n == N) {
-        tile_body_unrolled<C, N, K>(d, start, tab);
-    } else if constexpr (N > 0) {
-        dispatch_wg<C, N - 1, K>(n, d, start, tab);
-    }
-}
-
-// one workgroup per tile: the hardware dispatcher hands out the tiles in table order
-// (longest first), no work counter; binary64 bodies read the exp table through L1,
-// binary32 bodies stage it in LDS, as the plain kernels do
-template <int MAXN, int K>
-__global__ __launch_bounds__(256) void k_batched_wg(const Desc *__restrict__ descs,
-                                                    const int2 *__restrict__ tiles,
-                                                    int32_t tile_args)
-{
-    __shared__ double2 lds_tab[256];
-    const int2 ts = tiles[blockIdx.x];
-    const int32_t a = __builtin_amdgcn_readfirstlane(ts.x);
-    const Desc d = descs[a];
-    const int64_t start = (int64_t)__builtin_amdgcn_readfirstlane(ts.y) * tile_args;
-    const int n = __builtin_amdgcn_readfirstlane(d.n_max);
-    const int prec = __builtin_amdgcn_readfirstlane(d.prec);
-    const double2 *gtab = reinterpret_cast<const double2 *>(boys_tab::kExp2Tab);
-    if (prec == BOYS_FP64) {
-        dispatch_wg<BOYS_FP64, cmin(MAXN, class_max<BOYS_FP64>()), K>(n, d, start, gtab);
-    } else if (prec == BOYS_FP32) {
-        load_exp_table(lds_tab);
-        dispatch_wg<BOYS_FP32, cmin(MAXN, class_max<BOYS_FP32>()), K>(n, d, start, lds_tab);
-    } else if (prec == BOYS_FP32X) {
-        dispatch_wg<BOYS_FP32X, cmin(MAXN, class_max<BOYS_FP32X>()), K>(n, d, start, gtab);
-    } else {
-        dispatch_wg<BOYS_FP64_PLUS, cmin(MAXN, class_max<BOYS_FP64_PLUS>()), K>(n, d, start, gtab);
-    }
-}
-
-__global__ void k_reset(uint32_t *counter)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0)
-        *counter = 0u;
-}
 
 // ---------------------------------------------------------------------------------
 // host helpers
@@ -302,36 +54,22 @@ int cu_count()
     return g_cu_count[dev];
 }
 
-using PlainLaunch = hipError_t (*)(const double *, int64_t, void *, int64_t, hipStream_t);
+using boys_internal::PlainLaunch;
 
-template <int C, int N>
-hipError_t launch_plain(const double *x, int64_t n, void *out, int64_t ld, hipStream_t s)
+PlainLaunch plain_launcher(int32_t prec, int n)
 {
-    constexpr int kBlock = plain_block<C>();
-    constexpr int64_t kChunk = (int64_t)INT32_MAX / kBlock * kBlock;  // one grid's worth
-    using T = std::conditional_t<C == BOYS_FP32 || C == BOYS_FP32X, float, double>;
-    for (int64_t off = 0; off < n; off += kChunk) {
-        const int64_t cnt = std::min(kChunk, n - off);
-        const int grid = (int)((cnt + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL((k_plain<C, N>), dim3(grid), dim3(kBlock), 0, s, x + off, cnt,
-                           static_cast<void *>(static_cast<T *>(out) + off), ld);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess)
-            return e;
+    switch (prec) {
+    case BOYS_FP64:
+        return boys_internal::plain_launcher<BOYS_FP64>(n);
+    case BOYS_FP32:
+        return boys_internal::plain_launcher<BOYS_FP32>(n);
+    case BOYS_FP64_PLUS:
+        return boys_internal::plain_launcher<BOYS_FP64_PLUS>(n);
+    case BOYS_FP32X:
+        return boys_internal::plain_launcher<BOYS_FP32X>(n);
     }
-    return hipSuccess;
+    return nullptr;
 }
-
-template <int C, int... Ns>
-constexpr std::array<PlainLaunch, sizeof...(Ns)> plain_table(std::integer_sequence<int, Ns...>)
-{
-    return {&launch_plain<C, Ns>...};
-}
-
-const auto kPlain64 = plain_table<BOYS_FP64>(std::make_integer_sequence<int, kMaxN64 + 1>{});
-const auto kPlain32 = plain_table<BOYS_FP32>(std::make_integer_sequence<int, kMaxN32 + 1>{});
-const auto kPlain64Plus = plain_table<BOYS_FP64_PLUS>(std::make_integer_sequence<int, kMaxN64>{});
-const auto kPlain32x = plain_table<BOYS_FP32X>(std::make_integer_sequence<int, kMaxN32x + 1>{});
 
 int max_nmax(int32_t prec)
 {
@@ -371,12 +109,6 @@ boys_status check_array(const double *x, int64_t n, int32_t n_max, const void *o
     return BOYS_OK;
 }
 
-// buckets of the batched kernels: the smallest MAXN >= the batch's largest n_max
-constexpr int kBuckets[] = {4, 8, 16, 24, kMaxN};
-constexpr int kNumBuckets = 5;
-using PersistentKernel = void (*)(const Desc *, const int2 *, int32_t, int32_t, uint32_t *);
-using WgKernel = void (*)(const Desc *, const int2 *, int32_t);
-
 int bucket_of(int maxn)
 {
     for (int b = 0; b < kNumBuckets; ++b)
@@ -385,27 +117,25 @@ int bucket_of(int maxn)
     return kNumBuckets - 1;
 }
 
-template <int... B>
-constexpr std::array<PersistentKernel, sizeof...(B)> persistent_table(std::integer_sequence<int, B...>)
-{
-    return {&k_batched<kBuckets[B]>...};
-}
-const auto kPersistent = persistent_table(std::make_integer_sequence<int, kNumBuckets>{});
+using BucketLaunch = hipError_t (*)(const Desc *, const int2 *, int32_t, uint32_t *,
+                                    const boys_internal::Launch &, hipStream_t);
 
 template <int K, int... B>
-constexpr std::array<WgKernel, sizeof...(B)> wg_table(std::integer_sequence<int, B...>)
+constexpr std::array<BucketLaunch, sizeof...(B)> bucket_table(std::integer_sequence<int, B...>)
 {
-    return {&k_batched_wg<kBuckets[B], K>...};
+    return {&boys_internal::launch_bucket<B, K>...};
 }
-const std::array<std::array<WgKernel, kNumBuckets>, 4> kWg = {
-    wg_table<1>(std::make_integer_sequence<int, kNumBuckets>{}),
-    wg_table<2>(std::make_integer_sequence<int, kNumBuckets>{}),
-    wg_table<4>(std::make_integer_sequence<int, kNumBuckets>{}),
-    wg_table<8>(std::make_integer_sequence<int, kNumBuckets>{})};
+
+// [shape][bucket]; shape 0 persistent, 1..3 one workgroup per tile with K = 1, 2, 4
+const std::array<std::array<BucketLaunch, kNumBuckets>, 4> kBucketLaunch = {
+    bucket_table<0>(std::make_integer_sequence<int, kNumBuckets>{}),
+    bucket_table<1>(std::make_integer_sequence<int, kNumBuckets>{}),
+    bucket_table<2>(std::make_integer_sequence<int, kNumBuckets>{}),
+    bucket_table<4>(std::make_integer_sequence<int, kNumBuckets>{})};
 
 int log2_small(int k)
 {
-    return k == 1 ? 0 : k == 2 ? 1 : k == 4 ? 2 : k == 8 ? 3 : -1;
+    return k == 1 ? 0 : k == 2 ? 1 : k == 4 ? 2 : -1;
 }
 
 }  // namespace
@@ -415,20 +145,12 @@ hipError_t boys_internal::launch_batched(const Desc *d_desc, const int2 *d_tiles
                                          hipStream_t s)
 {
     const int b = bucket_of(maxn);
-    if (L.schedule == 0) {
-        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, d_counter);
-        if (ntiles > 0)
-            hipLaunchKernelGGL(kPersistent[b], dim3(std::max(1, std::min(L.grid, ntiles))),
-                               dim3(L.block), 0, s, d_desc, d_tiles, ntiles, L.tile, d_counter);
-    } else {
-        const int k = log2_small(L.tile / L.block);
-        if (k < 0 || L.tile % L.block != 0)
-            return hipErrorInvalidValue;
-        if (ntiles > 0)
-            hipLaunchKernelGGL(kWg[k][b], dim3(ntiles), dim3(L.block), 0, s, d_desc, d_tiles,
-                               L.tile);
-    }
-    return hipGetLastError();
+    if (L.schedule == 0)
+        return kBucketLaunch[0][b](d_desc, d_tiles, ntiles, d_counter, L, s);
+    const int k = log2_small(L.tile / L.block);
+    if (k < 0 || L.tile % L.block != 0)
+        return hipErrorInvalidValue;
+    return kBucketLaunch[1 + k][b](d_desc, d_tiles, ntiles, d_counter, L, s);
 }
 
 int boys_internal::cu_count()
@@ -624,11 +346,29 @@ boys_status boys_eval(const double *x, int64_t n, int32_t n_max, void *out, int6
     if (st != BOYS_OK || n == 0)
         return st;
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    const hipError_t err = precision == BOYS_FP64   ? kPlain64[n_max](x, n, out, ld_out, s)
-                           : precision == BOYS_FP32 ? kPlain32[n_max](x, n, out, ld_out, s)
-                           : precision == BOYS_FP32X ? kPlain32x[n_max](x, n, out, ld_out, s)
-                                                     : kPlain64Plus[n_max](x, n, out, ld_out, s);
-    return err == hipSuccess ? BOYS_OK : BOYS_ERR_DEVICE;
+    const PlainLaunch launch = plain_launcher(precision, n_max);
+    if (launch == nullptr)
+        return BOYS_ERR_UNSUPPORTED_NMAX;
+    return launch(x, n, out, ld_out, s) == hipSuccess ? BOYS_OK : BOYS_ERR_DEVICE;
+}
+
+boys_status boys_eval_split(const double *x, int64_t n, int32_t n_bar, int32_t n_max, void *out,
+                            int64_t ld_out, void *stream)
+{
+    const boys_status st = check_array(x, n, n_max, out, ld_out, BOYS_FP64);
+    if (st != BOYS_OK)
+        return st;
+    if (n_bar < 0 || n_bar >= n_max)
+        return BOYS_ERR_UNSUPPORTED_NMAX;
+    if (n == 0)
+        return BOYS_OK;
+    const boys_internal::SplitLaunch launch = boys_internal::split_launcher(n_max);
+    if (launch == nullptr)
+        return BOYS_ERR_UNSUPPORTED_NMAX;
+    return launch(x, n, static_cast<double *>(out), ld_out, n_bar,
+                  static_cast<hipStream_t>(stream)) == hipSuccess
+               ? BOYS_OK
+               : BOYS_ERR_DEVICE;
 }
 
 boys_status boys_plan_create(boys_plan **plan, const boys_array *arrays, int32_t count,

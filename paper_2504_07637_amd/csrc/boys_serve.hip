@@ -33,12 +33,12 @@ using boys_serve::Request;
 
 struct HipExec {
     int slots = 0;
-    int64_t tile = 2048;
+    int64_t tile = 256;
     int64_t cap_tiles = 65536;
     int max_batch = 256;
     int grid = 1024;
     int block = 256;
-    int schedule = 1;  // one workgroup per tile (tile = block x 1, 2, 4 or 8)
+    int schedule = 1;  // one workgroup per tile (tile = block x 1, 2 or 4)
     char *pool_base = nullptr;
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
@@ -189,7 +189,7 @@ boys_status boys_server_create(boys_server **out, const boys_server_config *cfg)
     const int tile = cfg->tile > 0 ? cfg->tile : 256;
     const int max_tiles = cfg->max_tiles > 0 ? cfg->max_tiles : 65536;
     if (cfg->budget_bytes <= 0 || streams > 32 || max_batch > 65536 ||
-        !(tile == 256 || tile == 512 || tile == 1024 || tile == 2048) || max_tiles > (1 << 24))
+        !(tile == 256 || tile == 512 || tile == 1024) || max_tiles > (1 << 24))
         return BOYS_ERR_INVALID_ARGUMENT;
     boys_server *s = new (std::nothrow) boys_server();
     if (!s)

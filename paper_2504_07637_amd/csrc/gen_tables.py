@@ -4,6 +4,9 @@ The header holds, as hexadecimal floating-point literals:
   * per (precision class, n) the root-factored approximant of Eqs. pqz, pz, qz
     (F64Set: binary64, F32Set: binary32 values, F32xSet: the ~28-bit sets, binary64):
     c_n, the cut-off z_nb, q0, q1, q2 and the factor lists of u and v;
+  * the binary64 sets once more as one runtime-indexed table (RtSet headers and one
+    flat coefficient array), for the two-approximation option whose lower order is a
+    launch argument;
   * c_0 = sqrt(pi)/2 for the long-range limit past the cut-off (Eq. limf1);
   * the tables of the correctly rounded exponential: 2^(j/256) for j = 0..255 as
     double-double pairs, and ln2/256 split into three parts for an exact reduction.
@@ -91,6 +94,31 @@ def emit_record(r):
     return s
 
 
+def emit_runtime(recs, cls, nmax):
+    """RtSet headers and the flat coefficient array (per set: ug, uq, ul, vg, vq, vl)."""
+    heads, coefs = [], []
+    for n in range(nmax + 1):
+        r = recs[(cls, n)]
+        cnt = [len(r["ug"]), len(r["uq"]) // 2, len(r["ul"]),
+               len(r["vg"]), len(r["vq"]) // 2, len(r["vl"])]
+        heads.append("  {" + ", ".join(lit(r[k], False) for k in ("c", "z", "q0", "q1", "q2"))
+                     + ", " + ", ".join(str(c) for c in cnt) + f", {len(coefs)}}},")
+        for k in ("ug", "uq", "ul", "vg", "vq", "vl"):
+            coefs += r[k]
+    out = ["// the binary64 sets, indexed at run time",
+           "struct RtSet {",
+           "  double c, z, q0, q1, q2;",
+           "  int ug_n, uq_n, ul_n, vg_n, vq_n, vl_n;  // factor counts (uq, vq: pairs)",
+           "  int off;                                 // first coefficient in kRtCoef64",
+           "};",
+           f"constexpr RtSet kRt64[{nmax + 1}] = {{"] + heads + ["};",
+           f"constexpr double kRtCoef64[{len(coefs)}] = {{"]
+    for i in range(0, len(coefs), 4):
+        out.append("  " + ", ".join(lit(v, False) for v in coefs[i:i + 4]) + ",")
+    out.append("};")
+    return out
+
+
 def exp_tables():
     mp.mp.prec = 300
     ln2 = mp.log(2)
@@ -148,6 +176,7 @@ def main(dataset=DATASET, out=OUT):
         lines.append(emit_record(recs[("fp32", n)]))
     for n in range(max32x + 1):
         lines.append(emit_record(recs[("fp32x", n)]))
+    lines += emit_runtime(recs, "fp64", max64)
     lines.append("constexpr double kCut64[] = {" + ", ".join(
         lit(recs[("fp64", n)]["z"], False) for n in range(max64 + 1)) + "};")
     lines.append("constexpr double kCut32[] = {" + ", ".join(

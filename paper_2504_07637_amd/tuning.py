@@ -7,8 +7,8 @@ device, library build and a coarse signature of the batch, and keeps it in a JSO
 
 Tunable choices (the per-argument work is one sequential chain, so a lane always owns
 whole arguments): the schedule (persistent workgroups with a work counter, or one
-workgroup per tile), the workgroup size, the arguments per lane (tile = block x 1, 2, 4
-or 8 for one workgroup per tile), the tile order (longest first, array by array, or
+workgroup per tile), the workgroup size, the arguments per lane (tile = block x 1, 2
+or 4 for one workgroup per tile), the tile order (longest first, array by array, or
 grouped by class) and, for the persistent schedule, the tile size and the number of
 workgroups per compute unit.
 """

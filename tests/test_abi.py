@@ -49,6 +49,15 @@ def test_argument_errors_are_reported_before_any_launch():
     assert lib.boys_eval(fake, 10, -1, fake, 10, L.FP64, None) == L.ERR_UNSUPPORTED_NMAX
     big = lib.boys_max_nmax(L.FP64) + 1
     assert lib.boys_eval(fake, 10, big, fake, 10, L.FP64, None) == L.ERR_UNSUPPORTED_NMAX
+    # the two-approximation option: 0 <= n_bar < n_max <= the binary64 maximum
+    top = lib.boys_max_nmax(L.FP64)
+    assert lib.boys_eval_split(fake, 10, 4, 4, fake, 10, None) == L.ERR_UNSUPPORTED_NMAX
+    assert lib.boys_eval_split(fake, 10, -1, 4, fake, 10, None) == L.ERR_UNSUPPORTED_NMAX
+    assert lib.boys_eval_split(fake, 10, 0, top + 1, fake, 10, None) == L.ERR_UNSUPPORTED_NMAX
+    assert lib.boys_eval_split(fake, 10, 0, 0, fake, 10, None) == L.ERR_UNSUPPORTED_NMAX
+    assert lib.boys_eval_split(None, 10, 1, 4, fake, 10, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eval_split(fake, 10, 1, 4, fake, 9, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eval_split(None, 0, 1, 4, None, 0, None) == L.OK
     # n == 0 is a successful no-op, whatever the pointers
     assert lib.boys_eval(None, 0, 4, None, 0, L.FP32, None) == L.OK
     p = ctypes.c_void_p()
@@ -61,6 +70,8 @@ def test_argument_errors_are_reported_before_any_launch():
     bad = L.BoysTuning(100, 256, 4, 0, 1)  # tile not a multiple of the block
     arr[0].n = 0
     assert lib.boys_plan_create(ctypes.byref(p), arr, 1, ctypes.byref(bad)) == L.ERR_INVALID_ARGUMENT
+    eight = L.BoysTuning(2048, 256, 1, 1, 1)  # one workgroup per tile: K = 8 is not built
+    assert lib.boys_plan_create(ctypes.byref(p), arr, 1, ctypes.byref(eight)) == L.ERR_INVALID_ARGUMENT
     assert lib.boys_plan_execute(None, None) == L.ERR_INVALID_ARGUMENT
     lib.boys_plan_destroy(None)
 

@@ -181,6 +181,45 @@ def test_fp32x_within_half_a_binary32_ulp_of_the_exact_function(n):
     _say(f"[exact] fp32x n_max={n} correctly rounded: {rounded / (x.size * (n + 1)):.5f}")
 
 
+def _cutoff_straddle():
+    # every binary64 cut-off, and its neighbours, for the two-approximation option
+    z = np.array([orc.record("fp64", n)["z"] for n in range(37)])
+    return np.concatenate([z, np.nextafter(z, np.inf), np.nextafter(z, -np.inf)])
+
+
+def test_two_approximation_option_identical_every_pair():
+    # every (n_max, n_bar) pair: the oracle's definition (rows 0..n_bar of the order-n_bar
+    # evaluation over rows n_bar+1..n_max of the order-n_max one), bit for bit
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    x = np.concatenate([inputs.uniform_mix(4096, seed=61), inputs.integral_args(4096, seed=62),
+                        _special(), _cutoff_straddle()])
+    xd = torch.from_numpy(x).to("cuda")
+    top = boys.max_nmax("fp64")
+    for n in range(1, top + 1):
+        _say(f"[split] n_max={n} n_bar=0..{n - 1} count={x.size}")
+        plain = orc.approx_f64(x, n)
+        for nbar in range(n):
+            got = boys.boys_eval_split(xd, n, nbar).cpu().numpy()
+            want = np.concatenate([orc.approx_f64(x, nbar), plain[nbar + 1:]], axis=0)
+            msg = report_mismatch(f"split n_max={n} n_bar={nbar}", got, want)
+            assert not msg, msg
+
+
+@pytest.mark.parametrize("n", [1, 65, 4099, 100003])
+def test_two_approximation_option_ragged_and_padded(n):
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    x = inputs.integral_args(n, seed=n + 7)
+    xd = torch.from_numpy(x).to("cuda")
+    buf = torch.full((17, n + 29), -7.0, dtype=torch.float64, device="cuda")
+    boys.boys_eval_split(xd, 16, 5, out=buf[:, :n])
+    torch.cuda.synchronize()
+    b = buf.cpu().numpy()
+    assert np.all(b[:, n:] == -7.0)
+    assert same_bits(b[:, :n], orc.approx_split(x, 16, 5)).all()
+
+
 def test_empty_input_is_a_noop():
     torch = require_gpu()
     import paper_2504_07637_amd as boys

@@ -111,6 +111,40 @@ def test_fp32x_class_within_half_a_binary32_ulp(n):
         assert bad.size == 0, (n, m, x[bad[:3]], err[bad[:3]], tol[bad[:3]])
 
 
+@pytest.mark.parametrize("n,nbar", [(36, 0), (36, 16), (20, 4), (16, 8), (16, 15)])
+def test_two_approximation_option_improves_the_low_orders(n, nbar, table1):
+    # over [0, 1.2 z_n): rows above nbar are the order-n evaluation's; every row up to nbar
+    # is within the Table 1 bounds of row nbar; rows up to nbar-2 are never worse than
+    # the order-n recursion leaves them, and F_0 gains when the recursion saved is long.
+    # (F_nbar itself carries the order-nbar approximant's own error, the weakest column
+    # of Table 1, which can be below what a longer recursion recovers: measured 44.4 vs
+    # 46.7 bits at n = 36, nbar = 16.)
+    k = 1 << 14
+    z = orc.record("fp64", n)["z"]
+    x = np.arange(k) * (1.2 * z / k)
+    S = orc.approx_split(x, n, nbar)
+    P = orc.approx_f64(x, n)
+    assert np.array_equal(S[nbar + 1:], P[nbar + 1:])
+    t = table1[nbar]["fp64"]
+    ebn1 = t["ebn1"] if t["ebn1"] is not None else t["eb0"]
+    bounds = [min(t["eb0"], ebn1) - 1.0] * (nbar + 1)
+    if nbar >= 1:
+        bounds[nbar - 1] = ebn1 - 1.0
+    bounds[nbar] = t["ebn"] - 1.0
+    gain0 = None
+    for m in range(nbar + 1):
+        hi, lo = orc.exact_one(x, m)
+        bs = orc.bits(orc.rel_err(S[m], hi, lo))
+        bp = orc.bits(orc.rel_err(P[m], hi, lo))
+        assert bs >= bounds[m], (n, nbar, m, bs, bounds[m])
+        if m <= nbar - 2:
+            assert bs >= bp - 0.25, (n, nbar, m, bs, bp)
+        if m == 0:
+            gain0 = bs - bp
+    if n - nbar >= 8:
+        assert gain0 > 0.5, (n, nbar, gain0)
+
+
 def test_pin_detects_planted_mistakes():
     # a wrong q1, or swapping the gathered factors of u and v, breaks the Table 1 pin
     r = orc.record("fp64", 16)
