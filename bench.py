@@ -40,9 +40,11 @@ N_ARGS = 1 << 26
 N_MAX = 16
 SPLIT_NBAR = 8   # the two-approximation option: rows 0..8 from the order-8 approximant
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6   # MI355X binary64 vector peak (an fma counts 2)
 TRAFFIC_FILE = os.path.join(REPO, "profiles", "traffic_boys_f64_n16.json")
 KERNEL_SOURCES = [os.path.join(REPO, "paper_2504_07637_amd", "csrc", f)
-                  for f in ("boys_device.h", "boys_kernels.h", "plain_inst.hip", "boys_tables.inc")]
+                  for f in ("boys_device.h", "boys_kernels.h", "plain_inst.hip", "eri_inst.hip",
+                            "boys_tables.inc")]
 
 
 def kernel_hash() -> str:
@@ -62,6 +64,9 @@ def parse():
                     help="target length of the CPU-baseline sample")
     ap.add_argument("--skip-extras", action="store_true",
                     help="only the headline (for profiling runs)")
+    ap.add_argument("--workload", choices=("boys", "eri"), default="boys",
+                    help="boys: the headline bulk evaluation (default); eri: the consumer "
+                         "kernel on its own (contracted (ss|ss)^(m) integrals)")
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="first run one elementwise kernel over 1 GiB (1 GiB read, 1 GiB "
                          "written), a dispatch of known traffic for scaling rocprofv3 "
@@ -172,6 +177,51 @@ def batched(torch, boys, inputs, steps):
     return res
 
 
+ERI_PAIRS = 2048   # contracted shell pairs on each side (9 primitive pairs each)
+ERI_FLOPS_FILE = os.path.join(REPO, "profiles", "flops_eri_ssss_n16.json")
+
+
+def eri(torch, boys, inputs, steps, warmup):
+    """The consumer: contracted (ss|ss)^(m), m = 0..16, over ERI_PAIRS^2 contracted pairs."""
+    c, e, w = inputs.s_basis()
+    pairs, start = inputs.shell_pairs(c, e, w, max_pairs=ERI_PAIRS)
+    P = torch.from_numpy(pairs).to("cuda")
+    S = torch.from_numpy(start).to("cuda")
+    nc = start.size - 1
+    out = boys.empty_out(nc * nc, N_MAX, "fp64")
+    wall, gpu = timed(torch, lambda: boys.boys_eri_ssss(P, S, P, S, N_MAX, out=out), steps,
+                      warmup)
+    launch_s = gpu / steps
+    prim = float(pairs.shape[1]) ** 2
+    res = {"workload": f"contracted (ss|ss)^(m), m = 0..{N_MAX}: {nc} x {nc} contracted pairs "
+                       f"of an s basis (32 atoms, 8 shells of 3 primitives each), "
+                       f"{int(prim)} primitive quartets, x = rho|PQ|^2 formed on the device",
+           "launch_ms": launch_s * 1e3, "ms_per_step": wall / steps * 1e3,
+           "quartets_per_s": nc * nc / launch_s,
+           "boys_evaluations_per_s": prim / launch_s,
+           "values_consumed_per_s": prim * (N_MAX + 1) / launch_s,
+           "bytes_stored_per_launch": 8 * (N_MAX + 1) * nc * nc}
+    fl = flops_for(kernel_hash())
+    if fl is not None:
+        res["roofline"] = {"bound": "alu", "achieved": fl / launch_s / 1e12,
+                           "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                           "frac": fl / launch_s / 1e12 / PEAK_FP64_TFLOPS,
+                           "flops_per_launch": fl, "kernel": f"k_eri_ssss<{N_MAX}>",
+                           "source": "executed binary64 VALU operations by counters"}
+    return res
+
+
+def flops_for(hash_now):
+    """Executed binary64 FLOPs per consumer launch (counter runs), if the kernels have not
+    changed since they were taken."""
+    try:
+        with open(ERI_FLOPS_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    return d.get("flops_per_launch") if d.get("kernel_hash") == hash_now else None
+
+
 def serving(torch, duration=1.0):
     from paper_2504_07637_amd import inputs
     from paper_2504_07637_amd import serving as srv_mod
@@ -217,6 +267,16 @@ def main():
         torch.mul(a, 2.0, out=b)  # one elementwise kernel: 1 GiB read, 1 GiB written
         torch.cuda.synchronize()
         del a, b
+    if args.workload == "eri":
+        r = eri(torch, boys, inputs, args.steps, args.warmup)
+        line = {"metric": "contracted (ss|ss)^(m) integrals/s at n_max=16 (consumer)",
+                "value": r["quartets_per_s"], "unit": "quartets/s", "n_gpus": 1,
+                "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f64", "data": "synthetic", "config": {"workload": r["workload"]}}
+        line.update({k: v for k, v in r.items() if k not in line and k != "workload"})
+        print(json.dumps(line), flush=True)
+        return
     x = inputs.integral_args(N_ARGS, seed=2)
     xd = torch.from_numpy(x).to("cuda")
     out64 = torch.empty((N_MAX + 1, N_ARGS), dtype=torch.float64, device="cuda")
@@ -282,6 +342,7 @@ def main():
         res["latency"] = latency(torch, boys, inputs)
         res["batched"] = batched(torch, boys, inputs, max(3, args.steps // 2))
         res["serving"] = serving(torch)
+        res["eri"] = eri(torch, boys, inputs, max(3, args.steps // 2), 2)
         res["cpu_baseline"] = cpu_baseline(x, args.cpu_seconds)
     print(json.dumps(res), flush=True)
 

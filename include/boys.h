@@ -96,6 +96,45 @@ boys_status boys_eval(const double *x, int64_t n, int32_t n_max, void *out, int6
 boys_status boys_eval_split(const double *x, int64_t n, int32_t n_bar, int32_t n_max, void *out,
                             int64_t ld_out, void *stream);
 
+/*
+ * A consumer of F_m that never stores them: the contracted (ss|ss)^(m) auxiliary
+ * two-electron integrals over s-type Gaussian functions, the application the paper names
+ * for the Boys functions (section "Introduction"), with x formed on the device.
+ *
+ * A primitive pair of Gaussians (exponents a, b at centres A, B) enters as its product:
+ * p = a + b, P = (a A + b B)/p and a weight w (contraction coefficients times
+ * exp(-ab/p |AB|^2)).  For a bra pair (p, P, w_a) and a ket pair (q, Q, w_b), with
+ * rho = pq/(p+q) and T = rho |P - Q|^2,
+ *     (ss|ss)^(m) = w_a w_b 2 pi^(5/2) / (p q sqrt(p+q)) F_m(T),   m = 0..n_max,
+ * with F_m the BOYS_FP64 evaluation of order n_max; a contracted pair sums over its
+ * primitive pairs, bra primitives outer and ket primitives inner, in the order below:
+ *     pq = p*q; spq = p+q; rho = pq/spq; d = P - Q; r2 = (dx*dx + dy*dy) + dz*dz;
+ *     T = rho*r2; s = (w_a*w_b) * (K / (pq*sqrt(spq))); acc_m = acc_m + s*F_m(T),
+ * K = 2 pi^(5/2) rounded to binary64.  Each output is a plain sequential sum, so results
+ * are reproducible bit for bit.
+ */
+typedef struct {
+    const double *p;       /* device: exponent sums p of the primitive pairs            */
+    const double *px;      /* device: product centres P, x component                    */
+    const double *py;      /* device: y component                                       */
+    const double *pz;      /* device: z component                                       */
+    const double *w;       /* device: weights                                           */
+    const int32_t *start;  /* device, count+1 entries: contracted pair c owns primitive
+                              pairs start[c] .. start[c+1]-1 (non-decreasing, start[0] >= 0;
+                              the caller guarantees it, the library cannot check device data) */
+    int32_t count;         /* contracted pairs in the list (>= 0)                       */
+} boys_pair_list;
+
+/*
+ * out[m * ld_out + i * ket->count + j] = the contracted (ss|ss)^(m) of bra contracted pair
+ * i and ket contracted pair j, m = 0..n_max (binary64; out is a device pointer).
+ * Requires ld_out >= bra->count * ket->count, 0 <= n_max <= boys_max_nmax(BOYS_FP64).
+ * Empty lists are a no-op.  BOYS_ERR_INVALID_ARGUMENT for null lists or pointers, negative
+ * counts or a short ld_out; BOYS_ERR_UNSUPPORTED_NMAX for n_max out of range.
+ */
+boys_status boys_eri_ssss(const boys_pair_list *bra, const boys_pair_list *ket, int32_t n_max,
+                          double *out, int64_t ld_out, void *stream);
+
 /* One argument array of a batch (host struct; x and out are device pointers). */
 typedef struct {
     const double *x;

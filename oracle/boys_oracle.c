@@ -36,6 +36,10 @@
  *      coefficients, i.e. the approximant in (nearly) exact arithmetic, for the
  *      exact-arithmetic error E_n of Eq. e.
  *
+ *   5. oracle_eri_ssss: a consumer of F_m, the contracted (ss|ss)^(m) auxiliary
+ *      two-electron integrals of s-type Gaussians (the application the paper names),
+ *      with x = rho |PQ|^2 formed from the pair data and every sum in a fixed order.
+ *
  * Readings where the paper leaves the arithmetic open or is misprinted (all also used by
  * the GPU library, which implements them independently):
  *   - Eq. r is printed with the divisor 2m+1; integrating d/dt(t^(2m-1) exp(-x t^2)) over
@@ -271,6 +275,38 @@ static void asymptote_d(double x, double c0, int nmax, double *F, int64_t stride
     }
 }
 
+/* F~_m(xi), m = 0..r->n, in binary64 into F[m * stride] */
+static void approx_one_d(const record *r, double xi, double *F, int64_t stride)
+{
+    const int n = r->n;
+    if (!(xi >= 0)) {
+        for (int m = 0; m <= n; ++m)
+            F[(int64_t)m * stride] = NAN;
+        return;
+    }
+    if (isinf(xi)) {
+        for (int m = 0; m <= n; ++m)
+            F[(int64_t)m * stride] = 0.0;
+        return;
+    }
+    if (xi > r->z) {
+        asymptote_d(xi, r->c0, n, F, stride);
+        return;
+    }
+    const double e = exp_rn(-xi);
+    const double u = factors_d(xi, r->ug, r->pug, r->uq, r->puq, r->ul, r->pul);
+    const double v = factors_d(xi, r->vg, r->pvg, r->vq, r->pvq, r->vl, r->pvl);
+    const double Q = r->q0 + r->q1 * xi + r->q2 * (u / v) * xi * xi;
+    const double W = powi_d(Q, n) * sqrt(Q) * e;
+    const double G = xi + W;
+    double Fm = r->c / (powi_d(G, n) * sqrt(G));
+    F[(int64_t)n * stride] = Fm;
+    for (int m = n; m >= 1; --m) {
+        Fm = (2.0 * xi * Fm + e) / (2 * m - 1);
+        F[(int64_t)(m - 1) * stride] = Fm;
+    }
+}
+
 /* 2. F~_m, m = 0..n, in binary64; out is (n+1) x count, row m at offset m*ld */
 int oracle_boys_approx_f64(const double *x, int64_t count, const double *rec, int reclen,
                            double *out, int64_t ld)
@@ -278,38 +314,9 @@ int oracle_boys_approx_f64(const double *x, int64_t count, const double *rec, in
     record r;
     if (parse_record(rec, reclen, &r) || count < 0 || ld < count)
         return 1;
-    const int n = r.n;
 #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < count; ++i) {
-        const double xi = x[i];
-        double *F = out + i;
-        if (!(xi >= 0)) {
-            for (int m = 0; m <= n; ++m)
-                F[(int64_t)m * ld] = NAN;
-            continue;
-        }
-        if (isinf(xi)) {
-            for (int m = 0; m <= n; ++m)
-                F[(int64_t)m * ld] = 0.0;
-            continue;
-        }
-        if (xi > r.z) {
-            asymptote_d(xi, r.c0, n, F, ld);
-            continue;
-        }
-        const double e = exp_rn(-xi);
-        const double u = factors_d(xi, r.ug, r.pug, r.uq, r.puq, r.ul, r.pul);
-        const double v = factors_d(xi, r.vg, r.pvg, r.vq, r.pvq, r.vl, r.pvl);
-        const double Q = r.q0 + r.q1 * xi + r.q2 * (u / v) * xi * xi;
-        const double W = powi_d(Q, n) * sqrt(Q) * e;
-        const double G = xi + W;
-        double Fm = r.c / (powi_d(G, n) * sqrt(G));
-        F[(int64_t)n * ld] = Fm;
-        for (int m = n; m >= 1; --m) {
-            Fm = (2.0 * xi * Fm + e) / (2 * m - 1);
-            F[(int64_t)(m - 1) * ld] = Fm;
-        }
-    }
+    for (int64_t i = 0; i < count; ++i)
+        approx_one_d(&r, x[i], out + i, ld);
     return 0;
 }
 
@@ -428,5 +435,69 @@ int oracle_exp_neg(const double *x, int64_t count, double *out)
 {
     for (int64_t i = 0; i < count; ++i)
         out[i] = exp_rn(-x[i]);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------ */
+/* 5. a consumer of F_m: contracted (ss|ss)^(m) auxiliary integrals                 */
+/*
+ * Two-electron repulsion integrals over s-type Gaussians (the paper's context: the
+ * Boys functions are the special functions of Gaussian-basis one- and two-electron
+ * integrals).  A primitive pair of exponents a, b at centres A, B is its Gaussian
+ * product: p = a + b, P = (a A + b B)/p, and a weight w that carries the contraction
+ * coefficients and exp(-ab/p |AB|^2).  For a bra pair (p, P, w_a) and a ket pair
+ * (q, Q, w_b), with rho = pq/(p+q) and T = rho |P - Q|^2,
+ *     (ss|ss)^(m) = w_a w_b 2 pi^(5/2) / (p q sqrt(p + q)) F_m(T),
+ * and a contracted pair sums over its primitive pairs.  The arithmetic, in this order:
+ *     pq = p*q;  spq = p+q;  rho = pq/spq;  d = P - Q (per component);
+ *     r2 = (dx*dx + dy*dy) + dz*dz;  T = rho*r2;  s = (w_a*w_b) * (K / (pq*sqrt(spq)));
+ *     acc_m = acc_m + s*F_m(T)   for bra primitives in order, ket primitives inner,
+ * K = 2 pi^(5/2) rounded once to binary64 and F_m the binary64 evaluation above.
+ *
+ * Pair lists: pairs[k*ldp + j] holds component k = (p, Px, Py, Pz, w) of primitive pair
+ * j; contracted pair c owns primitive pairs start[c] .. start[c+1]-1.  out[m*ld + i*nket
+ * + j] is the integral of bra contracted pair i with ket contracted pair j.
+ */
+double oracle_eri_prefactor(void)
+{
+    return (double)(2.0Q * M_PIq * M_PIq * sqrtq(M_PIq));
+}
+
+int oracle_eri_ssss(const double *rec, int reclen, const double *bra, int64_t ldb,
+                    const int32_t *bstart, int32_t nbra, const double *ket, int64_t ldk,
+                    const int32_t *kstart, int32_t nket, double *out, int64_t ld)
+{
+    record r;
+    if (parse_record(rec, reclen, &r) || nbra < 0 || nket < 0 || ld < (int64_t)nbra * nket)
+        return 1;
+    const int n = r.n;
+    const double K = oracle_eri_prefactor();
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t ij = 0; ij < (int64_t)nbra * nket; ++ij) {
+        const int32_t i = (int32_t)(ij / nket), j = (int32_t)(ij % nket);
+        double acc[64], F[64];
+        for (int m = 0; m <= n; ++m)
+            acc[m] = 0.0;
+        for (int32_t a = bstart[i]; a < bstart[i + 1]; ++a) {
+            const double p = bra[a], px = bra[ldb + a], py = bra[2 * ldb + a],
+                         pz = bra[3 * ldb + a], wa = bra[4 * ldb + a];
+            for (int32_t b = kstart[j]; b < kstart[j + 1]; ++b) {
+                const double q = ket[b], qx = ket[ldk + b], qy = ket[2 * ldk + b],
+                             qz = ket[3 * ldk + b], wb = ket[4 * ldk + b];
+                const double pq = p * q;
+                const double spq = p + q;
+                const double rho = pq / spq;
+                const double dx = px - qx, dy = py - qy, dz = pz - qz;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double T = rho * r2;
+                const double sc = (wa * wb) * (K / (pq * sqrt(spq)));
+                approx_one_d(&r, T, F, 1);
+                for (int m = 0; m <= n; ++m)
+                    acc[m] = acc[m] + sc * F[m];
+            }
+        }
+        for (int m = 0; m <= n; ++m)
+            out[(int64_t)m * ld + ij] = acc[m];
+    }
     return 0;
 }

@@ -17,6 +17,7 @@ approx_f32x(x, n)         the binary32-output class computed in binary64 (the ~2
                           approximant, each value rounded once), shape (n+1, len(x)), float32.
 approx_split(x, n, nbar)  the two-approximation option: rows 0..nbar of approx_f64(x, nbar)
                           over rows nbar+1..n of approx_f64(x, n).
+eri_ssss(...)             a consumer of F_m: contracted (ss|ss)^(m) integrals of s Gaussians.
 approx_exact_n(x, n)      F~_n in binary128 from the 40-digit coefficients, as (hi, lo).
 exp_neg(x)                correctly rounded exp(-x) as both approximants use it.
 load_dataset(path)        the parsed coefficient dataset.
@@ -64,6 +65,12 @@ def lib():
         L.oracle_boys_approx_mixed.argtypes = [dp, i64, dp, ctypes.c_int, fp, i64]
         L.oracle_boys_approx_q.argtypes = [dp, i64, dp, dp, dp]
         L.oracle_exp_neg.argtypes = [dp, i64, dp]
+        ip = ctypes.POINTER(ctypes.c_int32)
+        L.oracle_eri_ssss.argtypes = [dp, ctypes.c_int, dp, i64, ip, ctypes.c_int32, dp, i64, ip,
+                                      ctypes.c_int32, dp, i64]
+        L.oracle_eri_ssss.restype = ctypes.c_int
+        L.oracle_eri_prefactor.argtypes = []
+        L.oracle_eri_prefactor.restype = ctypes.c_double
         for f in (L.oracle_boys_exact, L.oracle_boys_exact_one, L.oracle_boys_approx_f64, L.oracle_boys_approx_mixed,
                   L.oracle_boys_approx_q, L.oracle_exp_neg):
             f.restype = ctypes.c_int
@@ -267,6 +274,31 @@ def approx_split(x, n: int, nbar: int):
     lo = approx_f64(x, nbar)
     hi = approx_f64(x, n)
     return np.concatenate([lo, hi[nbar + 1:]], axis=0)
+
+
+def eri_prefactor() -> float:
+    """2 pi^(5/2) rounded to binary64, as the (ss|ss) oracle uses it."""
+    return float(lib().oracle_eri_prefactor())
+
+
+def eri_ssss(bra, bstart, ket, kstart, n: int):
+    """Contracted (ss|ss)^(m), m = 0..n (see boys_oracle.c, item 5): bra, ket are (5, k)
+    float64 arrays of (p, Px, Py, Pz, w); bstart, kstart int32 CSR offsets.  Returns
+    (n+1, n_bra * n_ket)."""
+    bra = np.ascontiguousarray(bra, dtype=np.float64)
+    ket = np.ascontiguousarray(ket, dtype=np.float64)
+    bstart = np.ascontiguousarray(bstart, dtype=np.int32)
+    kstart = np.ascontiguousarray(kstart, dtype=np.int32)
+    nb, nk = bstart.size - 1, kstart.size - 1
+    fr = flat_record(record("fp64", n))
+    out = np.empty((n + 1, nb * nk))
+    ip = ctypes.POINTER(ctypes.c_int32)
+    rc = lib().oracle_eri_ssss(_dp(fr), fr.size, _dp(bra), bra.shape[1],
+                               bstart.ctypes.data_as(ip), nb, _dp(ket), ket.shape[1],
+                               kstart.ctypes.data_as(ip), nk, _dp(out), max(1, nb * nk))
+    if rc:
+        raise ValueError("oracle_eri_ssss rejected its arguments")
+    return out
 
 
 def approx_exact_n(x, n: int, cls: str = "fp64", fields=None):

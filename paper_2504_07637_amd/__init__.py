@@ -16,7 +16,7 @@ import ctypes
 from . import _lib
 from ._lib import FP32, FP32X, FP64, FP64_PLUS, BoysArray, BoysError, BoysTuning
 
-__all__ = ["boys_eval", "boys_eval_split", "boys_eval_batched", "Plan", "autotune", "max_nmax", "cutoff",
+__all__ = ["boys_eval", "boys_eval_split", "boys_eri_ssss", "boys_eval_batched", "Plan", "autotune", "max_nmax", "cutoff",
            "precision_code", "padded_ld", "empty_out", "BoysError", "FP64", "FP32", "FP64_PLUS",
            "FP32X"]
 
@@ -117,6 +117,45 @@ def boys_eval_split(x, n_max: int, n_bar: int, out=None, stream=None):
                                         ctypes.c_void_p(out.data_ptr()), ld,
                                         _stream_ptr(stream, x.device))
     _lib.check(st, "boys_eval_split")
+    return out
+
+
+def _pair_list(pairs, start):
+    """pairs: float64 (5, n) device tensor of (p, Px, Py, Pz, w) rows with unit stride
+    along n; start: int32 (count+1,) device tensor."""
+    torch = _torch()
+    if (not isinstance(pairs, torch.Tensor) or pairs.dtype != torch.float64 or not pairs.is_cuda
+            or pairs.dim() != 2 or pairs.shape[0] != 5
+            or (pairs.shape[1] > 1 and pairs.stride(1) != 1)):
+        raise TypeError("pairs must be a float64 (5, n) device tensor with unit column stride")
+    if (not isinstance(start, torch.Tensor) or start.dtype != torch.int32 or not start.is_cuda
+            or start.dim() != 1 or not start.is_contiguous() or start.numel() < 1):
+        raise TypeError("start must be a contiguous int32 device tensor of count+1 entries")
+    rows = [ctypes.c_void_p(pairs[k].data_ptr()) for k in range(5)]
+    return _lib.BoysPairList(*rows, ctypes.c_void_p(start.data_ptr()), start.numel() - 1)
+
+
+def boys_eri_ssss(bra_pairs, bra_start, ket_pairs, ket_start, n_max: int, out=None,
+                  stream=None):
+    """Contracted (ss|ss)^(m), m = 0..n_max, for every (bra, ket) contracted pair: a
+    (n_max+1, n_bra * n_ket) float64 tensor (column i * n_ket + j).  The F_m are formed and
+    consumed on the device; see include/boys.h for the arithmetic."""
+    torch = _torch()
+    bra = _pair_list(bra_pairs, bra_start)
+    ket = _pair_list(ket_pairs, ket_start)
+    total = bra.count * ket.count
+    dev = bra_pairs.device
+    if out is None:
+        out = empty_out(total, n_max, FP64, dev)
+    elif (out.dtype != torch.float64 or out.dim() != 2 or out.shape[0] != n_max + 1
+          or out.shape[1] != total or out.stride(1) != 1):
+        raise ValueError("out must be a float64 (n_max+1, n_bra*n_ket) tensor")
+    ld = out.stride(0) if total > 0 else 1
+    with torch.cuda.device(dev):
+        st = _lib.lib().boys_eri_ssss(ctypes.byref(bra), ctypes.byref(ket), n_max,
+                                      ctypes.c_void_p(out.data_ptr()), ld,
+                                      _stream_ptr(stream, dev))
+    _lib.check(st, "boys_eri_ssss")
     return out
 
 

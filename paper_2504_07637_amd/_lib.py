@@ -26,6 +26,7 @@ ERR_DEVICE = 4
 EXPORTS = (
     "boys_eval",
     "boys_eval_split",
+    "boys_eri_ssss",
     "boys_eval_batched",
     "boys_plan_create",
     "boys_plan_update",
@@ -65,6 +66,12 @@ class BoysServerConfig(ctypes.Structure):
                 ("max_tiles", ctypes.c_int32)]
 
 
+class BoysPairList(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_void_p), ("px", ctypes.c_void_p), ("py", ctypes.c_void_p),
+                ("pz", ctypes.c_void_p), ("w", ctypes.c_void_p), ("start", ctypes.c_void_p),
+                ("count", ctypes.c_int32)]
+
+
 class BoysServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in (
         "submitted", "admitted", "launched", "completed", "released", "batches",
@@ -94,6 +101,9 @@ def lib():
         L.boys_eval.restype = ctypes.c_int
         L.boys_eval_split.argtypes = [vp, i64, i32, i32, vp, i64, vp]
         L.boys_eval_split.restype = ctypes.c_int
+        L.boys_eri_ssss.argtypes = [ctypes.POINTER(BoysPairList), ctypes.POINTER(BoysPairList),
+                                    i32, vp, i64, vp]
+        L.boys_eri_ssss.restype = ctypes.c_int
         L.boys_eval_batched.argtypes = [ctypes.POINTER(BoysArray), i32, vp]
         L.boys_eval_batched.restype = ctypes.c_int
         L.boys_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(BoysArray), i32,

@@ -5,9 +5,9 @@
 Steps: regenerate csrc/boys_tables.inc from data/boys_coeffs.txt; compile, in parallel,
 the host side (csrc/boys_lib.hip), the serving loop (csrc/boys_serve.hip), the plain
 kernels once per precision class (csrc/plain_inst.hip) and the batched kernels once per
-(n_max bucket, launch shape) (csrc/batched_inst.hip), and the two-approximation
-kernels (csrc/split_inst.hip) into objects under _build/; link
-them into paper_2504_07637_amd/libboys.so.  BOYS_BUILD_JOBS caps the parallel compiles
+(n_max bucket, launch shape) (csrc/batched_inst.hip), the two-approximation kernels
+(csrc/split_inst.hip) and the consumer kernels (csrc/eri_inst.hip) into objects under
+_build/; link them into paper_2504_07637_amd/libboys.so.  BOYS_BUILD_JOBS caps the parallel compiles
 (default: the CPU count, at most 16).
 """
 from __future__ import annotations
@@ -66,7 +66,7 @@ def _units():
     units = [(f"batched_b{b}_k{k}", "batched_inst.hip", [f"-DBOYS_BUCKET={b}", f"-DBOYS_K={k}"])
              for b in reversed(range(BUCKETS)) for k in sorted(SHAPES, reverse=True)]
     units += [(f"plain_c{c}", "plain_inst.hip", [f"-DBOYS_CLASS={c}"]) for c in CLASSES]
-    units += [("split", "split_inst.hip", [])]
+    units += [("split", "split_inst.hip", []), ("eri", "eri_inst.hip", [])]
     units += [("boys_lib", "boys_lib.hip", []), ("boys_serve", "boys_serve.hip", [])]
     return units
 

@@ -1,10 +1,12 @@
 // boys_internal.h -- library-internal interface between the kernel instantiation units
-// (plain_inst.hip, batched_inst.hip, split_inst.hip), the host side (boys_lib.hip) and the serving
+// (plain_inst.hip, batched_inst.hip, split_inst.hip, eri_inst.hip), the host side (boys_lib.hip) and the serving
 // executor (boys_serve.hip).  Not part of the C ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "boys.h"
 
 namespace boys_internal {
 
@@ -47,6 +49,11 @@ PlainLaunch plain_launcher(int n);
 using SplitLaunch = hipError_t (*)(const double *x, int64_t n, double *out, int64_t ld,
                                    int nbar, hipStream_t s);
 SplitLaunch split_launcher(int n);
+
+// the consumer kernels (contracted (ss|ss)^(m) integrals) at order n_max; defined in
+// eri_inst.hip.  Arguments are checked by the caller.
+hipError_t launch_eri_ssss(const boys_pair_list &bra, const boys_pair_list &ket, int n_max,
+                           double *out, int64_t ld, hipStream_t s);
 
 // the batched kernel of n_max bucket B with launch shape K (0: persistent, [zero the
 // counter, kernel]; 1, 2, 4, 8: one workgroup per tile of K * L.block arguments); defined

@@ -22,6 +22,7 @@
 //   k_batched_wg<MAXN, K>  one workgroup per tile of K * blockDim arguments.
 //   k_split<N>       the two-approximation option (binary64, lower order a launch argument),
 //                    shaped as k_plain.
+//   k_eri_ssss<N>    a consumer: contracted (ss|ss)^(m) integrals, F_m never leave registers.
 //   k_reset          zeroes the tile counter (a kernel rather than a memset node, so the
 //                    plan's graph replays correctly).
 #pragma once
@@ -306,6 +307,29 @@ __global__ __launch_bounds__(128) void k_split(const double *__restrict__ x, int
         for (int m = 0; m <= N; ++m)
             __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
     }
+}
+
+// a consumer of F_m: contracted (ss|ss)^(m) auxiliary integrals (the arithmetic and its
+// order are fixed by the declaration of boys_eri_ssss).  One lane per contracted
+// (bra, ket) pair; T = rho |PQ|^2 is formed in registers, F_0..F_N are consumed there,
+// only the N+1 contracted sums are stored.
+using boys::PairList;
+
+template <int N>
+__global__ __launch_bounds__(256) void k_eri_ssss(PairList bra, PairList ket, double K,
+                                                  double *__restrict__ out, int64_t ld)
+{
+    const int64_t ij = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (ij >= (int64_t)bra.count * ket.count)
+        return;
+    const int32_t i = (int32_t)(ij / ket.count);
+    const int32_t j = (int32_t)(ij - (int64_t)i * ket.count);
+    double acc[N + 1];
+    boys::eri_ssss_one<N>(bra, ket, i, j, K, reinterpret_cast<const double2 *>(boys_tab::kExp2Tab),
+                          acc);
+#pragma unroll
+    for (int m = 0; m <= N; ++m)
+        __builtin_nontemporal_store(acc[m], out + (int64_t)m * ld + ij);
 }
 
 __global__ void k_reset(uint32_t *counter)

@@ -1,7 +1,7 @@
 // boys_lib.hip -- host side and C ABI of libboys.so (see include/boys.h): argument
 // checks, dispatch to the kernels (boys_kernels.h, instantiated in plain_inst.hip,
-// batched_inst.hip and split_inst.hip), batch schedules, plans with HIP graphs, the
-// autotuner.
+// batched_inst.hip, split_inst.hip and eri_inst.hip), batch schedules, plans with HIP
+// graphs, the autotuner.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -367,6 +367,29 @@ boys_status boys_eval_split(const double *x, int64_t n, int32_t n_bar, int32_t n
         return BOYS_ERR_UNSUPPORTED_NMAX;
     return launch(x, n, static_cast<double *>(out), ld_out, n_bar,
                   static_cast<hipStream_t>(stream)) == hipSuccess
+               ? BOYS_OK
+               : BOYS_ERR_DEVICE;
+}
+
+boys_status boys_eri_ssss(const boys_pair_list *bra, const boys_pair_list *ket, int32_t n_max,
+                          double *out, int64_t ld_out, void *stream)
+{
+    if (bra == nullptr || ket == nullptr || bra->count < 0 || ket->count < 0)
+        return BOYS_ERR_INVALID_ARGUMENT;
+    if (n_max < 0 || n_max > kMaxN64)
+        return BOYS_ERR_UNSUPPORTED_NMAX;
+    const int64_t total = (int64_t)bra->count * ket->count;
+    if (total == 0)
+        return BOYS_OK;
+    for (const boys_pair_list *l : {bra, ket})
+        if (!l->p || !l->px || !l->py || !l->pz || !l->w || !l->start)
+            return BOYS_ERR_INVALID_ARGUMENT;
+    if (out == nullptr || ld_out < total || ld_out > INT64_MAX / 8 / (int64_t)(n_max + 1))
+        return BOYS_ERR_INVALID_ARGUMENT;
+    if ((total + 255) / 256 > INT32_MAX)
+        return BOYS_ERR_INVALID_ARGUMENT;
+    return boys_internal::launch_eri_ssss(*bra, *ket, n_max, out, ld_out,
+                                          static_cast<hipStream_t>(stream)) == hipSuccess
                ? BOYS_OK
                : BOYS_ERR_DEVICE;
 }

@@ -7,7 +7,8 @@ The header holds, as hexadecimal floating-point literals:
   * the binary64 sets once more as one runtime-indexed table (RtSet headers and one
     flat coefficient array), for the two-approximation option whose lower order is a
     launch argument;
-  * c_0 = sqrt(pi)/2 for the long-range limit past the cut-off (Eq. limf1);
+  * c_0 = sqrt(pi)/2 for the long-range limit past the cut-off (Eq. limf1), and
+    2 pi^(5/2) for the (ss|ss) integrals of the consumer kernel;
   * the tables of the correctly rounded exponential: 2^(j/256) for j = 0..255 as
     double-double pairs, and ln2/256 split into three parts for an exact reduction.
 
@@ -183,6 +184,9 @@ def main(dataset=DATASET, out=OUT):
         lit(recs[("fp32", n)]["z"], False) for n in range(max32 + 1)) + "};")
     lines.append("constexpr double kCut32x[] = {" + (", ".join(
         lit(recs[("fp32x", n)]["z"], False) for n in range(max32x + 1)) or "0.0") + "};")
+    mp.mp.prec = 300
+    lines.append(f"constexpr double kTwoPi52 = {float.hex(float(2 * mp.pi ** 2.5))};"
+                 "  // 2 pi^(5/2), the (ss|ss) prefactor")
     lines.append("// exp(a) = 2^m 2^(j/256) exp(r), a = k ln2/256 + r, k = 256 m + j")
     lines.append(f"constexpr double kInvLn2x256 = {float.hex(inv)};")
     lines.append(f"constexpr double kLn2d256_1 = {float.hex(L1)};  // 36 significant bits")

@@ -15,6 +15,15 @@ stand in for the arguments that a Gaussian-basis integral code produces.
                         {0..16}, precision alternating binary64 / binary32 by index.
     serving_requests()  Poisson arrivals; lengths log-uniform in [64, 262144], n_max
                         uniform in {0..20}, precision binary64 or binary32 at 50/50.
+    s_basis()           s-type shells on atoms of a jittered cubic grid (2.6 bohr spacing,
+                        0.3 bohr jitter), 1..max_prim primitives per shell, exponents
+                        log-uniform in [0.05, 5e4], coefficients U[0.1, 1].
+    shell_pairs()       the Gaussian products of shell pairs (a seeded subset, or all
+                        s1 <= s2): per primitive pair p = a + b, P = (aA + bB)/p and the
+                        weight c_a c_b exp(-ab/p |AB|^2), as (5, n) rows (p, Px, Py, Pz, w)
+                        with int32 offsets per contracted pair.  This is how a Gaussian
+                        integral code prepares the pair data whose x = rho |PQ|^2 reaches
+                        the Boys functions; it is input preparation, not Boys arithmetic.
 """
 from __future__ import annotations
 
@@ -82,3 +91,45 @@ def serving_requests(rate: float = 20000.0, duration: float = 1.0, seed: int = 5
         out.append((t, int(np.rint(_log_uniform(g, min_len, max_len, 1))[0]),
                     int(g.integers(0, nmax_hi + 1)), int(g.integers(0, 2))))
     return out
+
+
+def s_basis(n_atoms: int = 32, shells_per_atom: int = 8, max_prim: int = 3, seed: int = 6,
+            fixed_prim: bool = True):
+    """(centres (S, 3), [exponents per shell], [coefficients per shell]); every shell has
+    max_prim primitives when fixed_prim, else 1..max_prim."""
+    g = rng(seed)
+    side = int(np.ceil(n_atoms ** (1.0 / 3.0)))
+    grid = np.array([(i, j, k) for i in range(side) for j in range(side) for k in range(side)],
+                    dtype=np.float64)[:n_atoms]
+    atoms = 2.6 * grid + g.normal(0.0, 0.3, (n_atoms, 3))
+    centres, exps, coefs = [], [], []
+    for a in range(n_atoms):
+        for _ in range(shells_per_atom):
+            k = max_prim if fixed_prim else int(g.integers(1, max_prim + 1))
+            centres.append(atoms[a])
+            exps.append(np.sort(_log_uniform(g, 0.05, 5e4, k))[::-1].copy())
+            coefs.append(g.uniform(0.1, 1.0, k))
+    return np.array(centres), exps, coefs
+
+
+def shell_pairs(centres, exps, coefs, max_pairs: int | None = None, seed: int = 7):
+    """(pairs (5, n_prim_pairs) float64, start (count+1,) int32) for the shell pairs."""
+    S = len(centres)
+    allp = [(i, j) for i in range(S) for j in range(i, S)]
+    if max_pairs is not None and max_pairs < len(allp):
+        g = rng(seed)
+        pick = np.sort(g.choice(len(allp), max_pairs, replace=False))
+        allp = [allp[k] for k in pick]
+    cols, start = [], [0]
+    for i, j in allp:
+        A, B = centres[i], centres[j]
+        ab2 = float(np.sum((A - B) ** 2))
+        for a, ca in zip(exps[i], coefs[i]):
+            for b, cb in zip(exps[j], coefs[j]):
+                p = a + b
+                P = (a * A + b * B) / p
+                cols.append((p, P[0], P[1], P[2], ca * cb * np.exp(-a * b / p * ab2)))
+        start.append(len(cols))
+    pairs = np.array(cols, dtype=np.float64).T.copy() if cols else np.zeros((5, 0))
+    return pairs, np.array(start, dtype=np.int32)
+

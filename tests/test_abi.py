@@ -58,6 +58,20 @@ def test_argument_errors_are_reported_before_any_launch():
     assert lib.boys_eval_split(None, 10, 1, 4, fake, 10, None) == L.ERR_INVALID_ARGUMENT
     assert lib.boys_eval_split(fake, 10, 1, 4, fake, 9, None) == L.ERR_INVALID_ARGUMENT
     assert lib.boys_eval_split(None, 0, 1, 4, None, 0, None) == L.OK
+    # the (ss|ss) consumer: list and argument checks happen on the host
+    fl = L.BoysPairList(fake, fake, fake, fake, fake, fake, 4)
+    neg = L.BoysPairList(fake, fake, fake, fake, fake, fake, -1)
+    nul = L.BoysPairList(fake, None, fake, fake, fake, fake, 4)
+    R = ctypes.byref
+    assert lib.boys_eri_ssss(None, R(fl), 4, fake, 16, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eri_ssss(R(neg), R(fl), 4, fake, 16, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eri_ssss(R(nul), R(fl), 4, fake, 16, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eri_ssss(R(fl), R(fl), 4, fake, 15, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eri_ssss(R(fl), R(fl), 4, None, 16, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eri_ssss(R(fl), R(fl), top + 1, fake, 16, None) == L.ERR_UNSUPPORTED_NMAX
+    assert lib.boys_eri_ssss(R(fl), R(fl), -1, fake, 16, None) == L.ERR_UNSUPPORTED_NMAX
+    zero = L.BoysPairList(None, None, None, None, None, None, 0)
+    assert lib.boys_eri_ssss(R(zero), R(fl), 4, None, 0, None) == L.OK
     # n == 0 is a successful no-op, whatever the pointers
     assert lib.boys_eval(None, 0, 4, None, 0, L.FP32, None) == L.OK
     p = ctypes.c_void_p()

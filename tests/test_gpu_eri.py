@@ -1,0 +1,75 @@
+"""GPU: the consumer kernel (contracted (ss|ss)^(m) integrals, F_m kept in registers)
+against the oracle, bit for bit: both sum the same terms in the same order, each term from
+the same binary64 Boys evaluation."""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_common import report_mismatch, require_gpu
+from oracle import oracle as orc
+from paper_2504_07637_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(torch, pairs, start):
+    return (torch.from_numpy(np.ascontiguousarray(pairs)).to("cuda"),
+            torch.from_numpy(np.ascontiguousarray(start, dtype=np.int32)).to("cuda"))
+
+
+@pytest.mark.parametrize("n", [0, 1, 4, 16, 36])
+def test_identical_to_the_oracle_ragged_primitives(n):
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    c, e, w = inputs.s_basis(8, 3, 4, seed=12, fixed_prim=False)
+    bra, bs = inputs.shell_pairs(c, e, w, max_pairs=150, seed=1)
+    ket, ks = inputs.shell_pairs(c, e, w, max_pairs=97, seed=2)
+    _say(f"[eri] n_max={n} bra={bs.size - 1} ket={ks.size - 1}")
+    got = boys.boys_eri_ssss(*_dev(torch, bra, bs), *_dev(torch, ket, ks), n)
+    torch.cuda.synchronize()
+    msg = report_mismatch(f"eri n_max={n}", got.cpu().numpy(), orc.eri_ssss(bra, bs, ket, ks, n))
+    assert not msg, msg
+
+
+def test_empty_lists_and_primitive_free_pairs():
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    bra = np.array([[1.0, 3.0], [0.0, 0.1], [0.0, 0.0], [0.0, 0.2], [1.0, 0.5]])
+    bs = np.array([0, 2], dtype=np.int32)
+    ket = np.array([[2.0], [0.5], [0.0], [0.0], [1.0]])
+    ks = np.array([0, 0, 1, 1], dtype=np.int32)  # pairs 0 and 2 have no primitives
+    got = boys.boys_eri_ssss(*_dev(torch, bra, bs), *_dev(torch, ket, ks), 5)
+    torch.cuda.synchronize()
+    want = orc.eri_ssss(bra, bs, ket, ks, 5)
+    assert np.array_equal(got.cpu().numpy(), want)
+    assert np.all(want[:, [0, 2]] == 0) and np.all(want[:, 1] > 0)
+    none = np.zeros((5, 0))
+    out = boys.boys_eri_ssss(*_dev(torch, bra, bs), *_dev(torch, none, np.array([0])), 5)
+    torch.cuda.synchronize()
+    assert out.shape == (6, 0)
+
+
+def test_full_size_workload_sampled():
+    # the benchmark's 2048 x 2048 contracted pairs (9 primitive pairs each), n_max = 16:
+    # 24 bra rows in full against the oracle
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    c, e, w = inputs.s_basis()
+    pairs, start = inputs.shell_pairs(c, e, w, max_pairs=2048)
+    nc = start.size - 1
+    _say(f"[eri] full {nc} x {nc}, n_max=16")
+    got = boys.boys_eri_ssss(*_dev(torch, pairs, start), *_dev(torch, pairs, start), 16)
+    torch.cuda.synchronize()
+    rows = np.unique(np.concatenate([[0, nc - 1], np.random.default_rng(9).integers(0, nc, 22)]))
+    for i in rows:
+        sub = pairs[:, start[i]:start[i + 1]]
+        want = orc.eri_ssss(sub, np.array([0, sub.shape[1]], dtype=np.int32), pairs, start, 16)
+        g = got[:, i * nc:(i + 1) * nc].cpu().numpy()
+        msg = report_mismatch(f"eri row {i}", g, want)
+        assert not msg, msg
