@@ -163,7 +163,7 @@ def batched(torch, boys, inputs, steps):
     from paper_2504_07637_amd import tuning
     best, info = tuning.tuned(xs, nm, pr)
     plan = boys.Plan(xs, nm, pr, tuning=best)
-    wall, gpu = timed(torch, plan.execute, steps, 2)
+    wall, gpu = timed(torch, plan.execute, steps, 10)
     values = sum(l * (m + 1) for l, m, _ in plan_spec)
     bytes_ = sum(l * (8 + (m + 1) * (8 if p == 0 else 4)) for l, m, p in plan_spec)
     ms = gpu / steps * 1e3
@@ -340,7 +340,7 @@ def main():
         del out64
         torch.cuda.empty_cache()
         res["latency"] = latency(torch, boys, inputs)
-        res["batched"] = batched(torch, boys, inputs, max(3, args.steps // 2))
+        res["batched"] = batched(torch, boys, inputs, max(30, args.steps))
         res["serving"] = serving(torch)
         res["eri"] = eri(torch, boys, inputs, max(3, args.steps // 2), 2)
         res["cpu_baseline"] = cpu_baseline(x, args.cpu_seconds)
