@@ -103,10 +103,17 @@ def cpu_baseline(x, target_s):
         if dt * 4 > target_s or n * 4 > x.size:
             break
         n *= 4
+    ne = 1 << 14
+    t0 = time.perf_counter()
+    orc.exact(x[:ne], N_MAX)
+    dte = time.perf_counter() - t0
     return {"value": (N_MAX + 1) * n / dt, "unit": "values/s", "cores": threads,
             "kind": "oracle",
             "sample": f"first {n} arguments of the same 2^26 workload, n_max=16, binary64 "
-                      f"approximant oracle (plain C, OpenMP, {dt:.2f} s)"}
+                      f"approximant oracle (plain C, OpenMP, {dt:.2f} s)",
+            "exact_oracle_values_per_s": (N_MAX + 1) * ne / dte,
+            "exact_oracle_sample": f"first {ne} arguments, F_0..F_16 from the definition in "
+                                   f"binary128 (OpenMP, {dte:.2f} s)"}
 
 
 def accuracy(torch, boys, xd, x):
@@ -144,10 +151,24 @@ def latency(torch, boys, inputs):
         torch.cuda.synchronize()
         ts.append(time.perf_counter() - t0)
     ts = np.array(ts) * 1e6
+    plan = boys.Plan([x], [4], ["fp64"], outs=[out])
+    for _ in range(20):
+        plan.execute()
+    torch.cuda.synchronize()
+    tg = []
+    for _ in range(1000):
+        t0 = time.perf_counter()
+        plan.execute()
+        torch.cuda.synchronize()
+        tg.append(time.perf_counter() - t0)
+    plan.close()
+    tg = np.array(tg) * 1e6
     return {"workload": "65,536 arguments (1/4 zeros, U[0,1], logU[1,50], logU[50,1e4]), "
-                        "n_max=4, binary64, call+synchronize",
+                        "n_max=4, binary64, call+synchronize, 1000 calls",
             "p50_us": round(float(np.percentile(ts, 50)), 2),
-            "p99_us": round(float(np.percentile(ts, 99)), 2)}
+            "p99_us": round(float(np.percentile(ts, 99)), 2),
+            "graph_p50_us": round(float(np.percentile(tg, 50)), 2),
+            "graph_p99_us": round(float(np.percentile(tg, 99)), 2)}
 
 
 def batched(torch, boys, inputs, steps):
@@ -167,10 +188,15 @@ def batched(torch, boys, inputs, steps):
     values = sum(l * (m + 1) for l, m, _ in plan_spec)
     bytes_ = sum(l * (8 + (m + 1) * (8 if p == 0 else 4)) for l, m, p in plan_spec)
     ms = gpu / steps * 1e3
+    # the same arrays as 8,192 separate boys_eval calls into the plan's outputs
+    solo = lambda: [boys.boys_eval(xi, m, p, out=o) for xi, m, p, o in zip(xs, nm, pr, plan.outs)]
+    solo_wall, solo_gpu = timed(torch, solo, 2, 1)
     res = {"workload": "8,192 arrays, lengths logU[32,65536], n_max U{0..16}, "
                        "binary64/binary32 alternating, one graph-captured batched launch",
            "arguments": total, "ms": round(ms, 4), "values_per_s": values / (gpu / steps),
            "hbm_GBs": bytes_ / (ms * 1e-3) / 1e9, "tuning": best,
+           "solo_calls_ms": round(solo_gpu / 2 * 1e3, 3),
+           "batching_gain": round(solo_gpu / 2 / (gpu / steps), 2),
            "tuning_cached": info["cached"],
            "candidates_ms": {k: round(v, 4) for k, v in info["times_ms"].items()}}
     plan.close()
@@ -222,19 +248,22 @@ def flops_for(hash_now):
     return d.get("flops_per_launch") if d.get("kernel_hash") == hash_now else None
 
 
-def serving(torch, duration=1.0):
+def serving(torch, duration=10.0):
     from paper_2504_07637_amd import inputs
     from paper_2504_07637_amd import serving as srv_mod
     pool = srv_mod.argument_pool(1 << 24, seed=5)
+    warm = inputs.serving_requests(rate=20000.0, duration=1.0, seed=50)
     reqs = inputs.serving_requests(rate=20000.0, duration=duration, seed=5)
     with srv_mod.Server(budget_bytes=8 << 30, streams=4) as srv:
-        srv_mod.run_poisson(srv, reqs[:2000], pool)   # warm-up
+        srv_mod.run_poisson(srv, warm, pool)   # 1 s warm-up, not reported
         res = srv_mod.run_poisson(srv, reqs, pool)
+        st = srv.stats()
     out = srv_mod.summarize(res)
+    out["max_admitted_bytes"] = st["max_bytes_in_use"]
     out["workload"] = ("Poisson 20,000 requests/s, lengths logU[64,262144], n_max U{0..20}, "
                        "binary64/binary32 50/50, integral-workload arguments, 8 GiB budget, "
-                       f"{duration:.1f} s; latency = completion - submission, host-to-device "
-                       "copies included")
+                       f"{duration:.0f} s of steady state after a 1 s warm-up; latency = "
+                       "completion - submission, host-to-device copies included")
     return out
 
 
@@ -333,6 +362,16 @@ def main():
                   "launch_ms": gpu32x / args.steps * 1e3,
                   "hbm_GBs": (8 + 4 * (N_MAX + 1)) * N_ARGS / (gpu32x / args.steps) / 1e9},
     }
+    # measured HBM figures on this device: one write stream (fill) and a read+write copy
+    wall_f, gpu_f = timed(torch, lambda: out64.fill_(1.0), 5, 2)
+    fill_GBs = out64.numel() * 8 / (gpu_f / 5) / 1e9
+    src = out64[:8].reshape(-1)
+    dst = out32[:16].view(torch.float64).reshape(-1)
+    wall_c, gpu_c = timed(torch, lambda: dst.copy_(src), 5, 2)
+    copy_GBs = 2 * src.numel() * 8 / (gpu_c / 5) / 1e9
+    res["roofline"]["measured_fill_GBs"] = fill_GBs
+    res["roofline"]["measured_copy_GBs"] = copy_GBs
+    res["roofline"]["frac_of_measured_fill"] = achieved / fill_GBs
     del out32
     torch.cuda.empty_cache()
     if not args.skip_extras:
