@@ -50,6 +50,31 @@ def _stream_ptr(stream, device):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+class _on_device:
+    """Make `device` current for the duration of a call (a no-op when it already is)."""
+
+    __slots__ = ("dev", "prev")
+
+    def __init__(self, device):
+        self.dev = device.index  # None: the current device
+        self.prev = None
+
+    def __enter__(self):
+        if self.dev is None:
+            return self
+        torch = _torch()
+        cur = torch.cuda.current_device()
+        if cur != self.dev:
+            self.prev = cur
+            torch.cuda.set_device(self.dev)
+        return self
+
+    def __exit__(self, *exc):
+        if self.prev is not None:
+            _torch().cuda.set_device(self.prev)
+        return False
+
+
 def padded_ld(n: int, precision) -> int:
     """Row stride (elements) that starts every output row on a 128-byte boundary.
 
@@ -92,9 +117,8 @@ def boys_eval(x, n_max: int, precision="fp64", out=None, stream=None):
         if out.shape[0] != n_max + 1 or out.shape[1] != n or out.stride(1) != 1:
             raise ValueError("out must be (n_max+1, n) with unit column stride")
     ld = out.stride(0) if n > 0 else max(n, 1)
-    with torch.cuda.device(x.device):
-        st = _lib.lib().boys_eval(ctypes.c_void_p(x.data_ptr()), n, n_max,
-                                  ctypes.c_void_p(out.data_ptr()), ld, code,
+    with _on_device(x.device):
+        st = _lib.lib().boys_eval(x.data_ptr(), n, n_max, out.data_ptr(), ld, code,
                                   _stream_ptr(stream, x.device))
     _lib.check(st, "boys_eval")
     return out
@@ -112,7 +136,7 @@ def boys_eval_split(x, n_max: int, n_bar: int, out=None, stream=None):
           or out.shape[0] != n_max + 1 or out.shape[1] != n or out.stride(1) != 1):
         raise ValueError("out must be a float64 (n_max+1, n) tensor with unit column stride")
     ld = out.stride(0) if n > 0 else 1
-    with torch.cuda.device(x.device):
+    with _on_device(x.device):
         st = _lib.lib().boys_eval_split(ctypes.c_void_p(x.data_ptr()), n, n_bar, n_max,
                                         ctypes.c_void_p(out.data_ptr()), ld,
                                         _stream_ptr(stream, x.device))
@@ -151,7 +175,7 @@ def boys_eri_ssss(bra_pairs, bra_start, ket_pairs, ket_start, n_max: int, out=No
           or out.shape[1] != total or out.stride(1) != 1):
         raise ValueError("out must be a float64 (n_max+1, n_bra*n_ket) tensor")
     ld = out.stride(0) if total > 0 else 1
-    with torch.cuda.device(dev):
+    with _on_device(dev):
         st = _lib.lib().boys_eri_ssss(ctypes.byref(bra), ctypes.byref(ket), n_max,
                                       ctypes.c_void_p(out.data_ptr()), ld,
                                       _stream_ptr(stream, dev))
@@ -185,7 +209,7 @@ def boys_eval_batched(xs, n_maxs, precisions, outs=None, stream=None):
     torch = _torch()
     arr, outs = _arrays(xs, n_maxs, precisions, outs)
     dev = xs[0].device if xs else torch.device("cuda")
-    with torch.cuda.device(dev):
+    with _on_device(dev):
         st = _lib.lib().boys_eval_batched(arr, len(xs), _stream_ptr(stream, dev))
     _lib.check(st, "boys_eval_batched")
     return outs
@@ -211,14 +235,14 @@ class Plan:
         self.device = xs[0].device if xs else torch.device("cuda")
         self._p = ctypes.c_void_p()
         t = _tuning(tuning)
-        with torch.cuda.device(self.device):
+        with _on_device(self.device):
             st = _lib.lib().boys_plan_create(ctypes.byref(self._p), self._arr, len(xs),
                                              ctypes.byref(t) if t is not None else None)
         _lib.check(st, "boys_plan_create")
 
     def execute(self, stream=None):
         torch = _torch()
-        with torch.cuda.device(self.device):
+        with _on_device(self.device):
             st = _lib.lib().boys_plan_execute(self._p, _stream_ptr(stream, self.device))
         _lib.check(st, "boys_plan_execute")
         return self.outs
@@ -253,7 +277,7 @@ def autotune(xs, n_maxs, precisions, candidates, warmup=2, reps=5, stream=None):
     best = BoysTuning()
     times = (ctypes.c_float * len(candidates))()
     dev = xs[0].device
-    with torch.cuda.device(dev):
+    with _on_device(dev):
         st = _lib.lib().boys_autotune(arr, len(xs), cand, len(candidates), warmup, reps,
                                       _stream_ptr(stream, dev), ctypes.byref(best), times)
     _lib.check(st, "boys_autotune")
