@@ -23,7 +23,7 @@ struct Desc {
 // how a batch is launched
 struct Launch {
     int schedule;  // 0: persistent workgroups + work counter; 1: one workgroup per tile
-    int tile;      // arguments per tile (schedule 1: block x 1, 2, 4 or 8)
+    int tile;      // arguments per tile (schedule 1: block x 1, 2 or 4)
     int block;     // threads per workgroup (64, 128, 256)
     int grid;      // schedule 0: number of persistent workgroups
 };
@@ -56,7 +56,7 @@ hipError_t launch_eri_ssss(const boys_pair_list &bra, const boys_pair_list &ket,
                            double *out, int64_t ld, hipStream_t s);
 
 // the batched kernel of n_max bucket B with launch shape K (0: persistent, [zero the
-// counter, kernel]; 1, 2, 4, 8: one workgroup per tile of K * L.block arguments); defined
+// counter, kernel]; 1, 2, 4: one workgroup per tile of K * L.block arguments); defined
 // per (B, K) in batched_inst.hip
 template <int B, int K>
 hipError_t launch_bucket(const Desc *d_desc, const int2 *d_tiles, int32_t ntiles,

@@ -262,3 +262,33 @@ def test_runs_on_a_side_stream():
         out = boys.boys_eval(xd, 16)
     s.synchronize()
     assert same_bits(out.cpu().numpy(), orc.approx_f64(x, 16)).all()
+
+
+def test_arrays_longer_than_one_grid():
+    # more than 2^31 arguments: the host splits the launch into grids of at most
+    # INT32_MAX / block workgroups' worth; check the arguments around every split point
+    # and a random sample (x drawn on the device from a seeded generator, n_max = 0)
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    n = (1 << 31) + 1000
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2024)
+    xd = torch.rand(n, dtype=torch.float64, device="cuda", generator=g) * 60.0
+    edges = []
+    for block in (128, 512):
+        chunk = (2**31 - 1) // block * block
+        edges += list(range(chunk - 300, min(n, chunk + 300)))
+    idx = np.unique(np.concatenate([np.arange(300), np.arange(n - 300, n), edges,
+                                    np.random.default_rng(3).integers(0, n, 1 << 14)]))
+    ti = torch.from_numpy(idx).to("cuda")
+    xs = xd[ti].cpu().numpy()
+    for prec in ("fp64", "fp32"):
+        _say(f"[huge] {prec} n={n} n_max=0")
+        out = boys.boys_eval(xd, 0, prec)
+        torch.cuda.synchronize()
+        got = out[:, ti].cpu().numpy()
+        want = orc.approx_f64(xs, 0) if prec == "fp64" else orc.approx_mixed(xs, 0)
+        msg = report_mismatch(f"huge {prec}", got, want)
+        assert not msg, msg
+        del out
+        torch.cuda.empty_cache()
