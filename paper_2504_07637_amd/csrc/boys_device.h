@@ -257,8 +257,11 @@ template <class S, int N>
 __host__ __device__ __forceinline__ void eval_f64_set(double x, const double2 *__restrict__ tab,
                                                       double (&F)[N + 1])
 {
+    // outside the domain (x < 0) the argument becomes NaN, which every step below carries
+    // into every row (fmax keeps the exponential's argument finite)
+    x = x >= 0.0 ? x : __builtin_nan("");
     if (!(x > S::z)) {
-        // below the cut-off (NaN and negative x also pass here and are replaced below)
+        // below the cut-off, and NaN
         const double e = exp_rn(__builtin_fmax(-x, -120.0), tab);
         const double u = factors<double, S::ug_n, S::uq_n, S::ul_n>(x, S::ug, S::uq, S::ul);
         const double v = factors<double, S::vg_n, S::vq_n, S::vl_n>(x, S::vg, S::vq, S::vl);
@@ -278,11 +281,6 @@ __host__ __device__ __forceinline__ void eval_f64_set(double x, const double2 *_
             f = f * (m - 0.5) * ix;
             F[m] = f;
         }
-    }
-    if (!(x >= 0.0)) {
-#pragma unroll
-        for (int m = 0; m <= N; ++m)
-            F[m] = __builtin_nan("");
     }
 }
 
@@ -389,6 +387,7 @@ __host__ __device__ __forceinline__ void eval_split(double x, int nbar,
                                                     double (&F)[N + 1])
 {
     static_assert(N >= 1, "the two-approximation option needs nbar < N");
+    x = x >= 0.0 ? x : __builtin_nan("");  // as in eval_f64_set
     using S = boys_tab::F64Set<N>;
     const boys_tab::RtSet &B = boys_tab::kRt64[nbar];
     const bool below_n = !(x > S::z);  // z_nbar < z_N: below_b implies below_n
@@ -421,11 +420,6 @@ __host__ __device__ __forceinline__ void eval_split(double x, int nbar,
         const double f = boys_tab::kC0 / __builtin_sqrt(x);
         F[0] = f;
         chain_up<N>(below_n ? nbar : N, ix, f, F);
-    }
-    if (!(x >= 0.0)) {
-#pragma unroll
-        for (int m = 0; m <= N; ++m)
-            F[m] = __builtin_nan("");
     }
 }
 
@@ -479,6 +473,7 @@ __host__ __device__ __forceinline__ void eval_f32(double x, const double2 *__res
                                                   float (&F)[N + 1])
 {
     using S = boys_tab::F32Set<N>;
+    x = x >= 0.0 ? x : __builtin_nan("");  // as in eval_f64_set
     if (!(x > S::z)) {
         const float xf = (float)x;
         const float e = (float)exp_rn(__builtin_fmax(-x, -120.0), tab);
@@ -499,11 +494,6 @@ __host__ __device__ __forceinline__ void eval_f32(double x, const double2 *__res
             f = f * (m - 0.5) * ix;
             F[m] = (float)f;
         }
-    }
-    if (!(x >= 0.0)) {
-#pragma unroll
-        for (int m = 0; m <= N; ++m)
-            F[m] = __builtin_nanf("");
     }
 }
 

@@ -53,6 +53,30 @@ using boys_internal::Desc;
 
 using boys_internal::Desc;
 
+// F_0..F_N of one argument to rows 0..N of the output (row stride ld), non-temporal.  The
+// address walks by ld: written as out + m*ld + i, the compiler forms each row address with
+// two 64-bit vector multiply-adds, which costs the VALU-bound classes measurably.
+template <int N, typename T>
+__device__ __forceinline__ void store_rows(const T *F, T *p, int64_t ld)
+{
+#pragma unroll
+    for (int m = 0; m <= N; ++m) {
+        __builtin_nontemporal_store(F[m], p);
+        p += ld;
+    }
+}
+
+// the same, each binary64 value rounded once to binary32
+template <int N>
+__device__ __forceinline__ void store_rows_f32(const double *F, float *p, int64_t ld)
+{
+#pragma unroll
+    for (int m = 0; m <= N; ++m) {
+        __builtin_nontemporal_store((float)F[m], p);
+        p += ld;
+    }
+}
+
 __device__ __forceinline__ void load_exp_table(double2 *tab)
 {
     for (int t = threadIdx.x; t < 256; t += blockDim.x)
@@ -66,9 +90,7 @@ __device__ __forceinline__ void body_f64(const double *__restrict__ x, double *_
 {
     double F[N + 1];
     boys::eval_f64<N>(__builtin_nontemporal_load(x + i), tab, F);
-#pragma unroll
-    for (int m = 0; m <= N; ++m)
-        __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
+    store_rows<N>(F, out + i, ld);
 }
 
 // binary64, F_0..F_N from the order N+1 approximant and one more recursion step
@@ -79,9 +101,7 @@ __device__ __forceinline__ void body_f64plus(const double *__restrict__ x,
 {
     double F[N + 2];
     boys::eval_f64<N + 1>(__builtin_nontemporal_load(x + i), tab, F);
-#pragma unroll
-    for (int m = 0; m <= N; ++m)
-        __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
+    store_rows<N>(F, out + i, ld);
 }
 
 // binary32 output from binary64 arithmetic with the ~28-bit approximants; each value is
@@ -92,9 +112,7 @@ __device__ __forceinline__ void body_f32x(const double *__restrict__ x, float *_
 {
     double F[N + 1];
     boys::eval_f32r<N>(__builtin_nontemporal_load(x + i), tab, F);
-#pragma unroll
-    for (int m = 0; m <= N; ++m)
-        __builtin_nontemporal_store((float)F[m], out + (int64_t)m * ld + i);
+    store_rows_f32<N>(F, out + i, ld);
 }
 
 // one argument of class C (a boys_precision value) at order N
@@ -107,9 +125,7 @@ __device__ __forceinline__ void body_f32(const double *__restrict__ x, float *__
 {
     float F[N + 1];
     boys::eval_f32<N>(__builtin_nontemporal_load(x + i), tab, F);
-#pragma unroll
-    for (int m = 0; m <= N; ++m)
-        __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
+    store_rows<N>(F, out + i, ld);
 }
 
 constexpr int cmin(int a, int b)
@@ -323,11 +339,10 @@ __global__ __launch_bounds__(128) void k_split(const double *__restrict__ x, int
     const int64_t i = (int64_t)block_index<xcd_contiguous<BOYS_FP64, N>()>() * 128 + threadIdx.x;
     if (i < n) {
         double F[N + 1];
-        boys::eval_split<N>(__builtin_nontemporal_load(x + i), nbar,
+        // nbar is a launch argument: say so, so that its tests stay scalar branches
+        boys::eval_split<N>(__builtin_nontemporal_load(x + i), __builtin_amdgcn_readfirstlane(nbar),
                             reinterpret_cast<const double2 *>(boys_tab::kExp2Tab), F);
-#pragma unroll
-        for (int m = 0; m <= N; ++m)
-            __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
+        store_rows<N>(F, out + i, ld);
     }
 }
 
