@@ -339,10 +339,13 @@ __global__ __launch_bounds__(128) void k_split(const double *__restrict__ x, int
     const int64_t i = (int64_t)block_index<xcd_contiguous<BOYS_FP64, N>()>() * 128 + threadIdx.x;
     if (i < n) {
         double F[N + 1];
-        // nbar is a launch argument: say so, so that its tests stay scalar branches
-        boys::eval_split<N>(__builtin_nontemporal_load(x + i), __builtin_amdgcn_readfirstlane(nbar),
+        boys::eval_split<N>(__builtin_nontemporal_load(x + i), nbar,
                             reinterpret_cast<const double2 *>(boys_tab::kExp2Tab), F);
-        store_rows<N>(F, out + i, ld);
+        // indexed row addresses here, not store_rows: with the pointer walk the compiler
+        // turns the branches on nbar into selects (static VALU count 812 against 755)
+#pragma unroll
+        for (int m = 0; m <= N; ++m)
+            __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
     }
 }
 
