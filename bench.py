@@ -48,10 +48,14 @@ KERNEL_SOURCES = [os.path.join(REPO, "paper_2504_07637_amd", "csrc", f)
 
 
 def kernel_hash() -> str:
+    """Hash of the kernel sources' code: // comments and blank lines do not count."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(p, "rb") as fh:
-            h.update(fh.read())
+        with open(p) as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -15,8 +15,8 @@
  * divisor of Eq. r as 2m+1; integration by parts of Eq. fn gives 2m-1.)
  *
  * Conventions for every entry point:
- *   - Pointers named x / out are DEVICE pointers (memory of the current HIP device);
- *     all other pointers are host pointers.  The caller owns all of them; the library
+ *   - Pointers named x / out, and the arrays a boys_pair_list points to, are DEVICE
+ *     pointers (memory of the current HIP device); all other pointers are host pointers.  The caller owns all of them; the library
  *     never frees or retains them beyond the call (plans keep the pointers they were
  *     given until updated or destroyed).
  *   - x is binary64, contiguous, n elements.

@@ -1,8 +1,8 @@
 // boys_kernels.h -- the device code of libboys.so: per-argument bodies and kernels.
 //
 // Included by the instantiation units (plain_inst.hip: the plain kernels of one precision
-// class; batched_inst.hip: the batched kernels of one n_max bucket and one launch shape),
-// which the build compiles in parallel.  Everything here has internal linkage, so each
+// class; batched_inst.hip: the batched kernels of one n_max bucket and one launch shape;
+// split_inst.hip and eri_inst.hip), which the build compiles in parallel.  Everything here has internal linkage, so each
 // unit holds only the kernels it instantiates.
 //
 // Kernels (gfx950, wave64):
@@ -13,7 +13,8 @@
 //                    row).  The binary64-output classes read the 4 KiB exp table through
 //                    the L1 cache with 128-thread workgroups; the binary32-output classes
 //                    stage it in LDS with 512-thread workgroups (the faster shape for each,
-//                    by measurement).
+//                    by measurement).  Outputs of 25+ binary64 rows take an XCD-contiguous
+//                    block order (xcd_contiguous below).
 //   k_batched<MAXN>  persistent workgroups pull tiles from a device counter; a tile is
 //                    one slice of one array, so (precision, n_max) is uniform per tile and
 //                    the per-tile dispatch is a scalar branch to the same unrolled bodies
@@ -47,9 +48,6 @@ constexpr int kMaxN = kMaxN64 > kMaxN32 ? (kMaxN64 > kMaxN32x ? kMaxN64 : kMaxN3
 // n_max buckets of the batched kernels: a batch runs the smallest MAXN >= its largest n_max
 constexpr int kBuckets[] = {4, 8, 16, 24, kMaxN};
 constexpr int kNumBuckets = 5;
-
-using boys_internal::Desc;
-
 
 using boys_internal::Desc;
 
