@@ -151,12 +151,15 @@ typedef struct {
  *             counter in table order;
  * schedule 1: one workgroup per tile, dispatched by the hardware in table order;
  *             tile must be block x 1, 2 or 4.
+ * schedule 2: one wave per tile (tile = 256, i.e. 64 lanes x 4 arguments; a block of
+ *             64, 128 or 256 holds block / 64 tiles), so one workgroup can serve several
+ *             short arrays.
  */
 typedef struct {
     int32_t tile;        /* arguments per tile, a multiple of the block size */
     int32_t block;       /* threads per workgroup: 64, 128 or 256 */
     int32_t grid_per_cu; /* schedule 0: persistent workgroups per compute unit (1..64) */
-    int32_t schedule;    /* 0 or 1 (above) */
+    int32_t schedule;    /* 0, 1 or 2 (above) */
     int32_t order;       /* tile order: 0 longest first; 1 array by array (each array's
                             tiles consecutive); 2 grouped by (precision, n_max), then
                             array by array */

@@ -27,7 +27,8 @@ BUILD_DIR = os.path.join(PKG, "_build")
 
 CLASSES = (0, 1, 2, 3)          # boys_precision values
 BUCKETS = 5                     # n_max buckets of the batched kernels
-SHAPES = (0, 1, 2, 4)           # 0: persistent; K: one workgroup per tile of K * block
+# (schedule, K): persistent; one workgroup per tile of K * block; one wave per tile of K * 64
+SHAPES = ((0, 0), (1, 1), (1, 2), (1, 4), (2, 4))
 ARCH = os.environ.get("BOYS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -63,8 +64,10 @@ def gen_tables() -> str:
 def _units():
     """(object name, source, extra flags) of every translation unit."""
     # the largest kernels (high buckets, large K) take longest: start them first
-    units = [(f"batched_b{b}_k{k}", "batched_inst.hip", [f"-DBOYS_BUCKET={b}", f"-DBOYS_K={k}"])
-             for b in reversed(range(BUCKETS)) for k in sorted(SHAPES, reverse=True)]
+    units = [(f"batched_b{b}_s{sc}_k{k}", "batched_inst.hip",
+              [f"-DBOYS_BUCKET={b}", f"-DBOYS_SCHED={sc}", f"-DBOYS_K={k}"])
+             for b in reversed(range(BUCKETS))
+             for sc, k in sorted(SHAPES, key=lambda t: -t[1])]
     units += [(f"plain_c{c}", "plain_inst.hip", [f"-DBOYS_CLASS={c}"]) for c in CLASSES]
     units += [("split", "split_inst.hip", []), ("eri", "eri_inst.hip", [])]
     units += [("boys_lib", "boys_lib.hip", []), ("boys_serve", "boys_serve.hip", [])]

@@ -22,8 +22,9 @@ struct Desc {
 
 // how a batch is launched
 struct Launch {
-    int schedule;  // 0: persistent workgroups + work counter; 1: one workgroup per tile
-    int tile;      // arguments per tile (schedule 1: block x 1, 2 or 4)
+    int schedule;  // 0: persistent workgroups + work counter; 1: one workgroup per tile;
+                   // 2: one wave per tile
+    int tile;      // arguments per tile (schedule 1: block x 1, 2 or 4; schedule 2: 256)
     int block;     // threads per workgroup (64, 128, 256)
     int grid;      // schedule 0: number of persistent workgroups
 };
@@ -55,10 +56,10 @@ SplitLaunch split_launcher(int n);
 hipError_t launch_eri_ssss(const boys_pair_list &bra, const boys_pair_list &ket, int n_max,
                            double *out, int64_t ld, hipStream_t s);
 
-// the batched kernel of n_max bucket B with launch shape K (0: persistent, [zero the
-// counter, kernel]; 1, 2, 4: one workgroup per tile of K * L.block arguments); defined
-// per (B, K) in batched_inst.hip
-template <int B, int K>
+// the batched kernel of n_max bucket B with schedule S (0: persistent, [zero the counter,
+// kernel]; 1: one workgroup per tile of K * L.block arguments, K = 1, 2, 4; 2: one wave
+// per tile of K * 64 arguments, K = 4); defined per (B, S, K) in batched_inst.hip
+template <int B, int S, int K>
 hipError_t launch_bucket(const Desc *d_desc, const int2 *d_tiles, int32_t ntiles,
                          uint32_t *d_counter, const Launch &L, hipStream_t s);
 

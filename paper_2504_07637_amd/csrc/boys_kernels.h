@@ -21,6 +21,7 @@
 //                    that k_plain uses, which makes batched results equal to solo ones
 //                    bit for bit.
 //   k_batched_wg<MAXN, K>  one workgroup per tile of K * blockDim arguments.
+//   k_batched_wave<MAXN, K>  one wave per tile of K * 64 arguments.
 //   k_split<N>       the two-approximation option (binary64, lower order a launch argument),
 //                    shaped as k_plain.
 //   k_eri_ssss<N>    a consumer: contracted (ss|ss)^(m) integrals, F_m never leave registers.
@@ -240,47 +241,53 @@ __device__ __forceinline__ void tile_strided(const double *x, void *out, int64_t
 }
 
 // K guarded iterations, fully unrolled (no loop): a tile of K * blockDim arguments
-template <int C, int N, int K>
+// (Wave: a tile of K * 64 arguments owned by one wave, the exp table read through L1 for
+// every class, so that the waves of a workgroup need no barrier)
+template <int C, int N, int K, bool Wave>
 __device__ __forceinline__ void tile_unrolled(const double *x, void *out, int64_t n, int64_t ld,
                                            int64_t start)
 {
     const Desc d{x, out, n, ld, N, C};
-    const double2 *tab = exp_tab<C>();
+    const double2 *tab =
+        Wave ? reinterpret_cast<const double2 *>(boys_tab::kExp2Tab) : exp_tab<C>();
+    const int stride = Wave ? 64 : (int)blockDim.x;
+    const int lane = Wave ? (int)(threadIdx.x & 63u) : (int)threadIdx.x;
 #pragma unroll
     for (int a = 0; a < K; ++a) {
-        const int64_t i = start + (int64_t)a * blockDim.x + threadIdx.x;
+        const int64_t i = start + (int64_t)a * stride + lane;
         if (i < n)
             body<C, N>(d, i, tab);
     }
 }
 
 // scalar dispatch over n (wave-uniform) to the tile functions of orders N, N-1, ..., 0;
-// K == 0 selects the strided form
-template <int C, int N, int K>
+// S: 0 the strided form (persistent schedule), 1 one workgroup per tile, 2 one wave per tile
+template <int C, int N, int S, int K>
 __device__ __forceinline__ void dispatch(int n, const Desc &d, int64_t start, int64_t cnt)
 {
     if (n == N) {
-        if constexpr (K == 0)
+        if constexpr (S == 0)
             tile_strided<C, N>(d.x, d.out, d.ld, start, cnt);
         else
-            tile_unrolled<C, N, K>(d.x, d.out, d.n, d.ld, start);
+            tile_unrolled<C, N, K, S == 2>(d.x, d.out, d.n, d.ld, start);
     } else if constexpr (N > 0) {
-        dispatch<C, N - 1, K>(n, d, start, cnt);
+        dispatch<C, N - 1, S, K>(n, d, start, cnt);
     }
 }
 
-template <int MAXN, int K>
+template <int MAXN, int S, int K>
 __device__ __forceinline__ void dispatch_class(int prec, int n, const Desc &d, int64_t start,
                                                int64_t cnt)
 {
     if (prec == BOYS_FP64)
-        dispatch<BOYS_FP64, cmin(MAXN, class_max<BOYS_FP64>()), K>(n, d, start, cnt);
+        dispatch<BOYS_FP64, cmin(MAXN, class_max<BOYS_FP64>()), S, K>(n, d, start, cnt);
     else if (prec == BOYS_FP32)
-        dispatch<BOYS_FP32, cmin(MAXN, class_max<BOYS_FP32>()), K>(n, d, start, cnt);
+        dispatch<BOYS_FP32, cmin(MAXN, class_max<BOYS_FP32>()), S, K>(n, d, start, cnt);
     else if (prec == BOYS_FP32X)
-        dispatch<BOYS_FP32X, cmin(MAXN, class_max<BOYS_FP32X>()), K>(n, d, start, cnt);
+        dispatch<BOYS_FP32X, cmin(MAXN, class_max<BOYS_FP32X>()), S, K>(n, d, start, cnt);
     else
-        dispatch<BOYS_FP64_PLUS, cmin(MAXN, class_max<BOYS_FP64_PLUS>()), K>(n, d, start, cnt);
+        dispatch<BOYS_FP64_PLUS, cmin(MAXN, class_max<BOYS_FP64_PLUS>()), S, K>(n, d, start,
+                                                                                 cnt);
 }
 
 template <int MAXN>
@@ -305,7 +312,7 @@ __global__ __launch_bounds__(256) void k_batched(const Desc *__restrict__ descs,
         const int64_t start = (int64_t)__builtin_amdgcn_readfirstlane(ts.y) * tile_args;
         const int64_t rem = d.n - start;
         const int64_t cnt = rem < tile_args ? rem : tile_args;
-        dispatch_class<MAXN, 0>(__builtin_amdgcn_readfirstlane(d.prec),
+        dispatch_class<MAXN, 0, 0>(__builtin_amdgcn_readfirstlane(d.prec),
                                 __builtin_amdgcn_readfirstlane(d.n_max), d, start, cnt);
     }
 }
@@ -325,7 +332,26 @@ __global__ __launch_bounds__(256) void k_batched_wg(const Desc *__restrict__ des
     const int prec = __builtin_amdgcn_readfirstlane(d.prec);
     if (prec == BOYS_FP32)
         load_exp_table(s_exp_tab);
-    dispatch_class<MAXN, K>(prec, __builtin_amdgcn_readfirstlane(d.n_max), d, start, 0);
+    dispatch_class<MAXN, 1, K>(prec, __builtin_amdgcn_readfirstlane(d.n_max), d, start, 0);
+}
+
+// one wave per tile: each wave of a workgroup takes its own tile of K * 64 arguments, so
+// one workgroup can serve several short arrays (a tile never spans two arrays)
+template <int MAXN, int K>
+__global__ __launch_bounds__(256) void k_batched_wave(const Desc *__restrict__ descs,
+                                                      const int2 *__restrict__ tiles,
+                                                      int32_t ntiles, int32_t tile_args)
+{
+    const int32_t w = __builtin_amdgcn_readfirstlane(
+        (int32_t)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    if (w >= ntiles)
+        return;
+    const int2 ts = tiles[w];
+    const int32_t a = __builtin_amdgcn_readfirstlane(ts.x);
+    const Desc d = descs[a];
+    const int64_t start = (int64_t)__builtin_amdgcn_readfirstlane(ts.y) * tile_args;
+    dispatch_class<MAXN, 2, K>(__builtin_amdgcn_readfirstlane(d.prec),
+                               __builtin_amdgcn_readfirstlane(d.n_max), d, start, 0);
 }
 
 // the two-approximation option (binary64): one lane per argument, as k_plain<BOYS_FP64, N>;

@@ -120,22 +120,33 @@ int bucket_of(int maxn)
 using BucketLaunch = hipError_t (*)(const Desc *, const int2 *, int32_t, uint32_t *,
                                     const boys_internal::Launch &, hipStream_t);
 
-template <int K, int... B>
+template <int S, int K, int... B>
 constexpr std::array<BucketLaunch, sizeof...(B)> bucket_table(std::integer_sequence<int, B...>)
 {
-    return {&boys_internal::launch_bucket<B, K>...};
+    return {&boys_internal::launch_bucket<B, S, K>...};
 }
 
-// [shape][bucket]; shape 0 persistent, 1..3 one workgroup per tile with K = 1, 2, 4
-const std::array<std::array<BucketLaunch, kNumBuckets>, 4> kBucketLaunch = {
-    bucket_table<0>(std::make_integer_sequence<int, kNumBuckets>{}),
-    bucket_table<1>(std::make_integer_sequence<int, kNumBuckets>{}),
-    bucket_table<2>(std::make_integer_sequence<int, kNumBuckets>{}),
-    bucket_table<4>(std::make_integer_sequence<int, kNumBuckets>{})};
+// [shape][bucket]; shape 0 persistent, 1..3 one workgroup per tile with K = 1, 2, 4,
+// 4 one wave per tile with K = 4
+const std::array<std::array<BucketLaunch, kNumBuckets>, 5> kBucketLaunch = {
+    bucket_table<0, 0>(std::make_integer_sequence<int, kNumBuckets>{}),
+    bucket_table<1, 1>(std::make_integer_sequence<int, kNumBuckets>{}),
+    bucket_table<1, 2>(std::make_integer_sequence<int, kNumBuckets>{}),
+    bucket_table<1, 4>(std::make_integer_sequence<int, kNumBuckets>{}),
+    bucket_table<2, 4>(std::make_integer_sequence<int, kNumBuckets>{})};
 
-int log2_small(int k)
+// row of kBucketLaunch for a tuning, -1 if that shape is not built
+int shape_row(int schedule, int tile, int block)
 {
-    return k == 1 ? 0 : k == 2 ? 1 : k == 4 ? 2 : -1;
+    if (schedule == 0)
+        return 0;
+    if (schedule == 1 && tile % block == 0) {
+        const int k = tile / block;
+        return k == 1 ? 1 : k == 2 ? 2 : k == 4 ? 3 : -1;
+    }
+    if (schedule == 2)
+        return tile == 256 ? 4 : -1;  // 64 lanes x 4 arguments
+    return -1;
 }
 
 }  // namespace
@@ -144,13 +155,10 @@ hipError_t boys_internal::launch_batched(const Desc *d_desc, const int2 *d_tiles
                                          uint32_t *d_counter, int maxn, const Launch &L,
                                          hipStream_t s)
 {
-    const int b = bucket_of(maxn);
-    if (L.schedule == 0)
-        return kBucketLaunch[0][b](d_desc, d_tiles, ntiles, d_counter, L, s);
-    const int k = log2_small(L.tile / L.block);
-    if (k < 0 || L.tile % L.block != 0)
+    const int row = shape_row(L.schedule, L.tile, L.block);
+    if (row < 0)
         return hipErrorInvalidValue;
-    return kBucketLaunch[1 + k][b](d_desc, d_tiles, ntiles, d_counter, L, s);
+    return kBucketLaunch[row][bucket_of(maxn)](d_desc, d_tiles, ntiles, d_counter, L, s);
 }
 
 int boys_internal::cu_count()
@@ -204,15 +212,13 @@ boys_tuning resolve(const boys_tuning *t)
 bool tuning_ok(const boys_tuning &t)
 {
     const bool block_ok = t.block == 64 || t.block == 128 || t.block == 256;
-    if (!block_ok || t.tile < t.block || t.tile % t.block != 0 || t.tile > (1 << 24))
+    if (!block_ok || t.tile <= 0 || t.tile > (1 << 24))
         return false;
     if (t.order < 0 || t.order > 2)
         return false;
     if (t.schedule == 0)
-        return t.grid_per_cu >= 1 && t.grid_per_cu <= 64;
-    if (t.schedule == 1)
-        return log2_small(t.tile / t.block) >= 0;
-    return false;
+        return t.tile % t.block == 0 && t.grid_per_cu >= 1 && t.grid_per_cu <= 64;
+    return shape_row(t.schedule, t.tile, t.block) >= 0;  // schedule 1: tile = block x K
 }
 
 boys_internal::Launch launch_of(const boys_plan *p)

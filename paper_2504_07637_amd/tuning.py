@@ -6,11 +6,11 @@ device, library build and a coarse signature of the batch, and keeps it in a JSO
 (``$BOYS_TUNING_FILE``, default ``~/.cache/paper_2504_07637_amd/tuning.json``).
 
 Tunable choices (the per-argument work is one sequential chain, so a lane always owns
-whole arguments): the schedule (persistent workgroups with a work counter, or one
-workgroup per tile), the workgroup size, the arguments per lane (tile = block x 1, 2
-or 4 for one workgroup per tile), the tile order (longest first, array by array, or
-grouped by class) and, for the persistent schedule, the tile size and the number of
-workgroups per compute unit.
+whole arguments): the schedule (persistent workgroups with a work counter, one workgroup
+per tile, or one wave per tile), the workgroup size, the arguments per lane (tile =
+block x 1, 2 or 4 for one workgroup per tile, 64 x 4 for one wave per tile), the
+tile order (longest first, array by array, or grouped by class) and, for the persistent
+schedule, the tile size and the number of workgroups per compute unit.
 """
 from __future__ import annotations
 
@@ -26,6 +26,8 @@ CANDIDATES = (
      for o in (1, 2, 0) for b in (128, 256) for k in (1, 2, 4)]
     + [{"schedule": 0, "block": 256, "tile": t, "grid_per_cu": g, "order": o}
        for o in (1, 0) for t in (1024, 4096) for g in (2, 4)]
+    + [{"schedule": 2, "block": b, "tile": 256, "grid_per_cu": 1, "order": o}
+       for o in (1, 2) for b in (128, 256)]
 )
 
 
@@ -76,8 +78,11 @@ def _store(path, data):
     os.replace(tmp, path)
 
 
-def tuned(xs, n_maxs, precisions, candidates=CANDIDATES, warmup=2, reps=5, refresh=False):
+def tuned(xs, n_maxs, precisions, candidates=CANDIDATES, warmup=12, reps=10, refresh=False):
     """The best tuning for this batch: from the cache, or measured now and cached.
+
+    Each candidate is a fresh plan; a fresh plan runs slower for about its first dozen
+    replays (measured), hence the warm-up before the timed replays.
 
     Returns (tuning dict, info dict with the key, whether it was cached and the times)."""
     import torch

@@ -86,6 +86,12 @@ def test_argument_errors_are_reported_before_any_launch():
     assert lib.boys_plan_create(ctypes.byref(p), arr, 1, ctypes.byref(bad)) == L.ERR_INVALID_ARGUMENT
     eight = L.BoysTuning(2048, 256, 1, 1, 1)  # one workgroup per tile: K = 8 is not built
     assert lib.boys_plan_create(ctypes.byref(p), arr, 1, ctypes.byref(eight)) == L.ERR_INVALID_ARGUMENT
+    for bad_wave in (L.BoysTuning(128, 256, 1, 2, 1), L.BoysTuning(512, 256, 1, 2, 1),
+                     L.BoysTuning(100, 64, 1, 2, 1), L.BoysTuning(256, 96, 1, 2, 1)):
+        # one wave per tile: 64 x 4 arguments only, block 64/128/256
+        assert lib.boys_plan_create(ctypes.byref(p), arr, 1, ctypes.byref(bad_wave)) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_plan_create(ctypes.byref(p), arr, 1, ctypes.byref(L.BoysTuning(256, 256, 1, 3, 1))) \
+        == L.ERR_INVALID_ARGUMENT  # no schedule 3
     assert lib.boys_plan_execute(None, None) == L.ERR_INVALID_ARGUMENT
     lib.boys_plan_destroy(None)
 

@@ -292,3 +292,20 @@ def test_arrays_longer_than_one_grid():
         assert not msg, msg
         del out
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n", [1, 127, 128 * 9 + 5, 128 * 17 + 3, 128 * 64 * 3 + 77])
+def test_xcd_block_order_lengths(n):
+    # binary64 outputs of 25+ rows take the XCD-contiguous block order: grids below 8
+    # blocks, grids that are not a multiple of 8 and a few hundred blocks, every row checked
+    torch = require_gpu()
+    x = np.concatenate([inputs.integral_args(n, seed=n + 3)[: max(0, n - 3)], [0.0, 80.0, 1e4]])[:n]
+    for prec, nm in (("fp64", 24), ("fp64", 36), ("fp64plus", 30)):
+        _say(f"[xcd] {prec} n_max={nm} n={n}")
+        got = _gpu_eval(torch, x, nm, prec, ld_pad=19)
+        msg = report_mismatch(f"xcd {prec} n_max={nm} n={n}", got, _oracle(x, nm, prec))
+        assert not msg, msg
+    import paper_2504_07637_amd as boys
+    xd = torch.from_numpy(x).to("cuda")
+    got = boys.boys_eval_split(xd, 30, 12).cpu().numpy()
+    assert same_bits(got, orc.approx_split(x, 30, 12)).all()
