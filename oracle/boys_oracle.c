@@ -30,7 +30,11 @@
  *
  *   3. oracle_boys_approx_mixed: the same approximant with the rational function, the
  *      power Q^(n+1/2) and the recursion in binary32 and only x + W and
- *      c_n / G^(n+1/2) in binary64.
+ *      c_n / G^(n+1/2) in binary64.  The classes with binary32 outputs (this one and
+ *      oracle_boys_approx_f64r for the ~28-bit sets) take each recursion step as a
+ *      multiplication by RN(1/(2m-1)) rather than a division: their outputs need far
+ *      less than the working precision, and the downward recursion damps the extra
+ *      rounding (the accuracy pins hold them to the same bounds).
  *
  *   4. oracle_boys_approx_q: F~_n alone in binary128 from extended-precision
  *      coefficients, i.e. the approximant in (nearly) exact arithmetic, for the
@@ -275,8 +279,9 @@ static void asymptote_d(double x, double c0, int nmax, double *F, int64_t stride
     }
 }
 
-/* F~_m(xi), m = 0..r->n, in binary64 into F[m * stride] */
-static void approx_one_d(const record *r, double xi, double *F, int64_t stride)
+/* F~_m(xi), m = 0..r->n, in binary64 into F[m * stride]; rcp != 0 takes the recursion
+   step as a multiplication by the rounded reciprocal of 2m-1 instead of a division */
+static void approx_one_d_(const record *r, double xi, double *F, int64_t stride, int rcp)
 {
     const int n = r->n;
     if (!(xi >= 0)) {
@@ -302,9 +307,17 @@ static void approx_one_d(const record *r, double xi, double *F, int64_t stride)
     double Fm = r->c / (powi_d(G, n) * sqrt(G));
     F[(int64_t)n * stride] = Fm;
     for (int m = n; m >= 1; --m) {
-        Fm = (2.0 * xi * Fm + e) / (2 * m - 1);
+        if (rcp)
+            Fm = (2.0 * xi * Fm + e) * (1.0 / (2 * m - 1));
+        else
+            Fm = (2.0 * xi * Fm + e) / (2 * m - 1);
         F[(int64_t)(m - 1) * stride] = Fm;
     }
+}
+
+static void approx_one_d(const record *r, double xi, double *F, int64_t stride)
+{
+    approx_one_d_(r, xi, F, stride, 0);
 }
 
 /* 2. F~_m, m = 0..n, in binary64; out is (n+1) x count, row m at offset m*ld */
@@ -317,6 +330,20 @@ int oracle_boys_approx_f64(const double *x, int64_t count, const double *rec, in
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < count; ++i)
         approx_one_d(&r, x[i], out + i, ld);
+    return 0;
+}
+
+/* 2'. the same in binary64 with the recursion step by the rounded reciprocal: the
+   evaluation of the ~28-bit sets for binary32 outputs (rounded by the caller) */
+int oracle_boys_approx_f64r(const double *x, int64_t count, const double *rec, int reclen,
+                            double *out, int64_t ld)
+{
+    record r;
+    if (parse_record(rec, reclen, &r) || count < 0 || ld < count)
+        return 1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < count; ++i)
+        approx_one_d_(&r, x[i], out + i, ld, 1);
     return 0;
 }
 
@@ -362,7 +389,8 @@ int oracle_boys_approx_mixed(const double *x, int64_t count, const double *rec, 
         float Fm = (float)(r.c / (powi_d(G, n) * sqrt(G)));
         F[(int64_t)n * ld] = Fm;
         for (int m = n; m >= 1; --m) {
-            Fm = (2.0f * xf * Fm + e) / (float)(2 * m - 1);
+            /* multiplication by the rounded reciprocal of 2m-1 (see the header) */
+            Fm = (2.0f * xf * Fm + e) * (1.0f / (float)(2 * m - 1));
             F[(int64_t)(m - 1) * ld] = Fm;
         }
     }

@@ -63,6 +63,8 @@ def lib():
         L.oracle_boys_exact_one.argtypes = [dp, i64, ctypes.c_int, dp, dp]
         L.oracle_boys_approx_f64.argtypes = [dp, i64, dp, ctypes.c_int, dp, i64]
         L.oracle_boys_approx_mixed.argtypes = [dp, i64, dp, ctypes.c_int, fp, i64]
+        L.oracle_boys_approx_f64r.argtypes = [dp, i64, dp, ctypes.c_int, dp, i64]
+        L.oracle_boys_approx_f64r.restype = ctypes.c_int
         L.oracle_boys_approx_q.argtypes = [dp, i64, dp, dp, dp]
         L.oracle_exp_neg.argtypes = [dp, i64, dp]
         ip = ctypes.POINTER(ctypes.c_int32)
@@ -260,10 +262,17 @@ def approx_mixed(x, n: int, rec: Record | None = None):
 
 
 def approx_f32x(x, n: int, rec: Record | None = None):
-    """The binary64 evaluation of the ~28-bit approximant (same steps as approx_f64, the
-    record's own cut-off), each value rounded to nearest binary32 once at the end."""
+    """The binary64 evaluation of the ~28-bit approximant (the steps of approx_f64 with the
+    record's own cut-off, each recursion step a multiplication by RN(1/(2m-1))), each
+    value rounded to nearest binary32 once at the end."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
     r = rec if rec is not None else record("fp32x", n)
-    return approx_f64(x, n, r).astype(np.float32)
+    fr = flat_record(r)
+    out = np.empty((n + 1, x.size))
+    rc = lib().oracle_boys_approx_f64r(_dp(x), x.size, _dp(fr), fr.size, _dp(out), x.size)
+    if rc:
+        raise ValueError("oracle_boys_approx_f64r rejected its arguments")
+    return out.astype(np.float32)
 
 
 def approx_split(x, n: int, nbar: int):

@@ -231,6 +231,26 @@ __host__ __device__ __forceinline__ void recurse_down(T x2, T e, T f, T *F)
     }
 }
 
+// the same recursion with each step a multiplication by RN(1/(2m-1)) instead of a
+// correctly rounded division: one operation instead of three, for the classes with
+// binary32 outputs, whose values need far less than the working precision (the downward
+// recursion damps the extra rounding)
+template <int M, typename T>
+__host__ __device__ __forceinline__ void recurse_down_rcp(T x2, T e, T f, T *F)
+{
+    if constexpr (M >= 1) {
+        T g = x2 * f + e;
+        if constexpr (M > 1) {
+            if constexpr (sizeof(T) == 8)
+                g = g * kOddRcp.d[M];
+            else
+                g = g * kOddRcp.f[M];
+        }
+        F[M - 1] = g;
+        recurse_down_rcp<M - 1, T>(x2, e, g, F);
+    }
+}
+
 // one of u, v: gathered monic polynomial (Horner), then quadratic, then linear factors
 template <typename T, int NG, int NQ, int NL>
 __host__ __device__ __forceinline__ T factors(T x, const T (&g)[NG > 0 ? NG : 1],
@@ -253,7 +273,7 @@ __host__ __device__ __forceinline__ T factors(T x, const T (&g)[NG > 0 ? NG : 1]
 // ---------------------------------------------------------------------------------
 // F_0..F_N for one argument, binary64 class
 
-template <class S, int N>
+template <class S, int N, bool RcpRecursion = false>
 __host__ __device__ __forceinline__ void eval_f64_set(double x, const double2 *__restrict__ tab,
                                                       double (&F)[N + 1])
 {
@@ -270,7 +290,10 @@ __host__ __device__ __forceinline__ void eval_f64_set(double x, const double2 *_
         const double G = x + W;
         const double f = S::c / (powi<N>(G) * __builtin_sqrt(G));
         F[N] = f;
-        recurse_down<N, double>(2.0 * x, e, f, F);
+        if constexpr (RcpRecursion)
+            recurse_down_rcp<N, double>(2.0 * x, e, f, F);
+        else
+            recurse_down<N, double>(2.0 * x, e, f, F);
     } else {
         // Eq. limf1 for every m; x = +inf gives 0 everywhere
         const double ix = 1.0 / x;
@@ -293,12 +316,13 @@ __host__ __device__ __forceinline__ void eval_f64(double x, const double2 *__res
 }
 
 // the binary32-output class computed in binary64: approximants of about 28 bits with the
-// cut-off z_{n,28}, every value rounded once to binary32 (by the caller)
+// cut-off z_{n,28}, the recursion by reciprocals, every value rounded once to binary32
+// (by the caller)
 template <int N>
 __host__ __device__ __forceinline__ void eval_f32r(double x, const double2 *__restrict__ tab,
                                                    double (&F)[N + 1])
 {
-    eval_f64_set<boys_tab::F32xSet<N>, N>(x, tab, F);
+    eval_f64_set<boys_tab::F32xSet<N>, N, true>(x, tab, F);
 }
 
 // ---------------------------------------------------------------------------------
@@ -484,7 +508,7 @@ __host__ __device__ __forceinline__ void eval_f32(double x, const double2 *__res
         const double G = x + (double)W;
         const float f = (float)(S::c / (powi<N>(G) * __builtin_sqrt(G)));
         F[N] = f;
-        recurse_down<N, float>(2.0f * xf, e, f, F);
+        recurse_down_rcp<N, float>(2.0f * xf, e, f, F);
     } else {
         const double ix = 1.0 / x;
         double f = boys_tab::kC0 / __builtin_sqrt(x);
