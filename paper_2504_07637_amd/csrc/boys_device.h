@@ -30,7 +30,10 @@
 //     is at least ulp/(2d) away from a rounding midpoint (t has a 53-bit or 24-bit
 //     significand and d is odd, so t/d cannot be a midpoint and differs from one by a
 //     multiple of ulp/(2d)), while q + (t - q d) r differs from t/d by less than
-//     2^-51 ulp.
+//     2^-51 ulp.  The classes with binary32 outputs take the step as one product
+//     RN(t * RN(1/d)) instead (recurse_down_rcp); their values need far less than the
+//     working precision;
+//   * x < 0 becomes NaN on entry, and NaN reaches every row through the arithmetic.
 //
 // The recursion divisor: the paper prints Eq. r with 2m+1; integrating
 // d/dt (t^(2m-1) exp(-x t^2)) over [0, 1] gives exp(-x) = (2m-1) F_{m-1} - 2x F_m.
