@@ -1,0 +1,75 @@
+"""Host-side logic of the Python binding and the benchmark (no device calls)."""
+import json
+import subprocess
+import sys
+import types
+
+import pytest
+
+import paper_2504_07637_amd as boys
+from paper_2504_07637_amd import _lib
+
+
+def test_precision_names():
+    for names, code in ((("fp64", "float64", "double", 0), _lib.FP64),
+                        (("fp32", "float32", "mixed", 1), _lib.FP32),
+                        (("fp64plus", "fp64+", 2), _lib.FP64_PLUS),
+                        (("fp32x", 3), _lib.FP32X)):
+        for nm in names:
+            assert boys.precision_code(nm) == code
+    for bad in ("fp16", 4, -1, None):
+        with pytest.raises(ValueError):
+            boys.precision_code(bad)
+
+
+def test_padded_row_stride_is_whole_cache_lines():
+    for n in (0, 1, 15, 16, 17, 31, 33, 1000, 65536):
+        for prec, es in (("fp64", 8), ("fp64plus", 8), ("fp32", 4), ("fp32x", 4)):
+            ld = boys.padded_ld(n, prec)
+            assert ld >= max(n, 1) and (ld * es) % 128 == 0 and ld * es - n * es < 128 + 128
+
+
+def test_device_guard_switches_only_when_needed(monkeypatch):
+    calls = []
+
+    class FakeCuda:
+        cur = 0
+
+        @staticmethod
+        def current_device():
+            return FakeCuda.cur
+
+        @staticmethod
+        def set_device(d):
+            calls.append(d)
+            FakeCuda.cur = d
+
+    monkeypatch.setattr(boys, "_torch", lambda: types.SimpleNamespace(cuda=FakeCuda))
+    with boys._on_device(types.SimpleNamespace(index=0)):
+        pass
+    with boys._on_device(types.SimpleNamespace(index=None)):
+        pass
+    assert calls == []
+    with boys._on_device(types.SimpleNamespace(index=2)):
+        assert FakeCuda.cur == 2
+    assert FakeCuda.cur == 0 and calls == [2, 0]
+
+
+def test_bench_refuses_more_than_one_gpu():
+    out = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert out.returncode == 2
+    line = json.loads(out.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def test_kernel_hash_ignores_comments(tmp_path, monkeypatch):
+    import bench
+    src = tmp_path / "k.h"
+    src.write_text("int a; // one\n\nint b;\n")
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", [str(src)])
+    h1 = bench.kernel_hash()
+    src.write_text("int a; // another comment\n// a comment line\nint b;\n")
+    assert bench.kernel_hash() == h1
+    src.write_text("int a;\nint c;\n")
+    assert bench.kernel_hash() != h1
