@@ -23,18 +23,20 @@ def _dev(torch, pairs, start):
             torch.from_numpy(np.ascontiguousarray(start, dtype=np.int32)).to("cuda"))
 
 
-@pytest.mark.parametrize("n", [0, 1, 4, 16, 36])
-def test_identical_to_the_oracle_ragged_primitives(n):
+def test_identical_to_the_oracle_every_order_ragged_primitives():
     torch = require_gpu()
     import paper_2504_07637_amd as boys
     c, e, w = inputs.s_basis(8, 3, 4, seed=12, fixed_prim=False)
     bra, bs = inputs.shell_pairs(c, e, w, max_pairs=150, seed=1)
     ket, ks = inputs.shell_pairs(c, e, w, max_pairs=97, seed=2)
-    _say(f"[eri] n_max={n} bra={bs.size - 1} ket={ks.size - 1}")
-    got = boys.boys_eri_ssss(*_dev(torch, bra, bs), *_dev(torch, ket, ks), n)
-    torch.cuda.synchronize()
-    msg = report_mismatch(f"eri n_max={n}", got.cpu().numpy(), orc.eri_ssss(bra, bs, ket, ks, n))
-    assert not msg, msg
+    B, K = _dev(torch, bra, bs), _dev(torch, ket, ks)
+    for n in range(boys.max_nmax("fp64") + 1):
+        _say(f"[eri] n_max={n} bra={bs.size - 1} ket={ks.size - 1}")
+        got = boys.boys_eri_ssss(*B, *K, n)
+        torch.cuda.synchronize()
+        msg = report_mismatch(f"eri n_max={n}", got.cpu().numpy(),
+                              orc.eri_ssss(bra, bs, ket, ks, n))
+        assert not msg, msg
 
 
 def test_empty_lists_and_primitive_free_pairs():
