@@ -231,7 +231,8 @@ def test_empty_input_is_a_noop():
 
 def test_full_size_integral_workload_sampled():
     # the 2^26-argument n_max = 16 workload in the launch configuration the benchmark
-    # times; the oracle checks 2^17 sampled arguments (and the first and last 4096)
+    # times, every class it times; the oracle checks 2^17 sampled arguments (and the
+    # first and last 4096)
     torch = require_gpu()
     import paper_2504_07637_amd as boys
     n_args = 1 << 26
@@ -240,12 +241,17 @@ def test_full_size_integral_workload_sampled():
     idx = np.unique(np.concatenate([np.arange(4096), np.arange(n_args - 4096, n_args),
                                     g.integers(0, n_args, 1 << 17)]))
     xd = torch.from_numpy(x).to("cuda")
-    for prec in ("fp64", "fp32"):
+    ti = torch.from_numpy(idx).to("cuda")
+    for prec in ("fp64", "fp32", "fp32x", "fp64plus", "split8"):
         _say(f"[full] {prec} n_max=16 count={n_args}")
-        out = boys.boys_eval(xd, 16, prec)
+        if prec == "split8":
+            out = boys.boys_eval_split(xd, 16, 8)
+            want = orc.approx_split(x[idx], 16, 8)
+        else:
+            out = boys.boys_eval(xd, 16, prec)
+            want = _oracle(x[idx], 16, prec)
         torch.cuda.synchronize()
-        got = out[:, torch.from_numpy(idx).to("cuda")].cpu().numpy()
-        want = orc.approx_f64(x[idx], 16) if prec == "fp64" else orc.approx_mixed(x[idx], 16)
+        got = out[:, ti].cpu().numpy()
         msg = report_mismatch(f"full {prec}", got, want)
         assert not msg, msg
         del out
