@@ -78,6 +78,11 @@ def parse():
     return ap.parse_args()
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def timed(torch, fn, steps, warmup):
     for _ in range(warmup):
         fn()
@@ -392,15 +397,22 @@ def main():
     res["roofline"]["frac_of_measured_fill"] = achieved / fill_GBs
     del out32
     torch.cuda.empty_cache()
+    progress(f"headline {ms64:.3f} ms per step")
     if not args.skip_extras:
         res["accuracy"] = accuracy(torch, boys, xd, x)
+        progress("accuracy done")
         del out64
         torch.cuda.empty_cache()
         res["latency"] = latency(torch, boys, inputs)
+        progress("latency done")
         res["batched"] = batched(torch, boys, inputs, max(30, args.steps))
+        progress("batched done")
         res["serving"] = serving(torch)
+        progress("serving done")
         res["eri"] = eri(torch, boys, inputs, max(3, args.steps // 2), 2)
+        progress("consumer done")
         res["cpu_baseline"] = cpu_baseline(x, args.cpu_seconds)
+        progress("cpu baseline done")
     print(json.dumps(res), flush=True)
 
 
