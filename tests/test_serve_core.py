@@ -121,3 +121,17 @@ def test_oversized_requests_are_refused(harness):
     ln = np.array([1000, 1000, 1000], dtype=np.int64)
     r = simulate(harness, t, ln, nm, pr, 1 << 30)
     assert list(r["rc"]) == [1, 0, 0] and r["done"] == 2
+
+
+def test_policy_core_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    # the pool fuzz and a simulated stream, host code only, built with ASan and UBSan
+    exe = tmp_path / "serve_core_sanitized"
+    cmd = ["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-I", CSRC, "-o", str(exe),
+           os.path.join(REPO, "tests", "native", "serve_core_sanitize.cpp"), SRC]
+    subprocess.check_call(cmd)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300, env=env)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert r.stdout.startswith("ok:"), r.stdout
