@@ -132,7 +132,7 @@ def accuracy(torch, boys, xd, x):
     ti = torch.from_numpy(idx).to(xd.device)
     out = {}
     hi, lo = orc.exact(x[idx], N_MAX)
-    for prec in ("fp64", "fp32", "fp32x", "fp64_split8"):
+    for prec in ("fp64", "fp32", "fp32x", "fp32s", "fp64_split8"):
         if prec == "fp64_split8":
             F = boys.boys_eval_split(xd, N_MAX, SPLIT_NBAR)[:, ti].cpu().numpy()
         else:
@@ -340,6 +340,8 @@ def main():
                           args.steps, args.warmup)
     wall32x, gpu32x = timed(torch, lambda: boys.boys_eval(xd, N_MAX, "fp32x", out=out32),
                             args.steps, args.warmup)
+    wall32s, gpu32s = timed(torch, lambda: boys.boys_eval(xd, N_MAX, "fp32s", out=out32),
+                            args.steps, args.warmup)
     wall_sp, gpu_sp = timed(torch, lambda: boys.boys_eval_split(xd, N_MAX, SPLIT_NBAR, out=out64),
                             args.steps, args.warmup)
     values = (N_MAX + 1) * N_ARGS
@@ -384,6 +386,11 @@ def main():
                   "speedup_vs_fp64": wall64 / wall32x,
                   "launch_ms": gpu32x / args.steps * 1e3,
                   "hbm_GBs": (8 + 4 * (N_MAX + 1)) * N_ARGS / (gpu32x / args.steps) / 1e9},
+        "fp32s": {"value": values * args.steps / wall32s, "unit": "values/s",
+                  "ms_per_step": wall32s / args.steps * 1e3,
+                  "speedup_vs_fp64": wall64 / wall32s,
+                  "launch_ms": gpu32s / args.steps * 1e3,
+                  "hbm_GBs": (8 + 4 * (N_MAX + 1)) * N_ARGS / (gpu32s / args.steps) / 1e9},
     }
     # measured HBM figures on this device: one write stream (fill) and a read+write copy
     wall_f, gpu_f = timed(torch, lambda: out64.fill_(1.0), 5, 2)

@@ -22,7 +22,7 @@
  *   - x is binary64, contiguous, n elements.
  *   - out holds (n_max + 1) rows of ld_out elements: F_m(x[i]) is at out[m * ld_out + i]
  *     (structure of arrays), binary64 for BOYS_FP64 / BOYS_FP64_PLUS and binary32 for
- *     BOYS_FP32 / BOYS_FP32X.
+ *     BOYS_FP32 / BOYS_FP32X / BOYS_FP32_SINGLE.
  *     Requires ld_out >= n.  Alignment: 8 bytes (FP64) or 4 bytes (FP32).  Rows that
  *     start on 128-byte boundaries (out 128-byte aligned and ld_out a multiple of 16
  *     binary64 / 32 binary32 elements) are written as whole cache lines; other strides
@@ -62,7 +62,12 @@ typedef enum {
        smallest N per n reaching 28 bits) and the cut-off z_{n_max,28}; each value is
        rounded once to binary32 at the store, so its error is within half a binary32 ulp
        plus 2^-28 relative (subnormal outputs: plus half the subnormal spacing) */
-    BOYS_FP32X = 3
+    BOYS_FP32X = 3,
+    /* all binary32 below the cut-off: the arithmetic of Table 1's binary32 columns, with
+       the binary32 sets, G = x + W in binary32 and F_n = (kappa_n / G)^(n+1/2), kappa_n =
+       c_n^(1/(n+1/2)) rounded to binary32 (c_n itself leaves the binary32 range beyond
+       n = 27); past the cut-off the long-range limit as BOYS_FP32; output binary32 */
+    BOYS_FP32_SINGLE = 4
 } boys_precision;
 
 typedef enum {
@@ -77,7 +82,7 @@ typedef enum {
  * Evaluate F_m(x[i]) for m = 0..n_max and i = 0..n-1 into out (layout above).
  * precision is a boys_precision value.  The approximant of order n_max is used
  * (coefficient set fitted for that n and that precision class, with the cut-off
- * z_{n_max,b}, b = 53 for BOYS_FP64, 24 for BOYS_FP32, 28 for BOYS_FP32X), and the lower orders come
+ * z_{n_max,b}, b = 53 for BOYS_FP64, 24 for BOYS_FP32 and BOYS_FP32_SINGLE, 28 for BOYS_FP32X), and the lower orders come
  * from the downward recursion of Eq. r below the cut-off and from Eq. limf1 above it.
  */
 boys_status boys_eval(const double *x, int64_t n, int32_t n_max, void *out, int64_t ld_out,

@@ -35,6 +35,8 @@
  *      multiplication by RN(1/(2m-1)) rather than a division: their outputs need far
  *      less than the working precision, and the downward recursion damps the extra
  *      rounding (the accuracy pins hold them to the same bounds).
+ *      oracle_boys_approx_single is the all-binary32 evaluation that Table 1's binary32
+ *      columns describe, with F_n = (kappa_n / G)^(n+1/2) to stay in range.
  *
  *   4. oracle_boys_approx_q: F~_n alone in binary128 from extended-precision
  *      coefficients, i.e. the approximant in (nearly) exact arithmetic, for the
@@ -398,6 +400,68 @@ int oracle_boys_approx_mixed(const double *x, int64_t count, const double *rec, 
 }
 
 /* ------------------------------------------------------------------------------ */
+/* 3'. the all-binary32 evaluation (the arithmetic of Table 1's binary32 columns) with
+   the binary32 sets: x, e, u/v, Q, W, G and F_n = (kappa_n / G)^(n+1/2) in binary32,
+   kappa_n = c_n^(1/(n+1/2)) rounded once to binary32 (c_n itself leaves the binary32
+   range beyond n = 27); the recursion by RN(1/(2m-1)) as in the mixed class; past the
+   cut-off the same long-range limit as the mixed class.  out is float.                */
+float oracle_kappa32(int n)
+{
+    const __float128 s = (__float128)n + 0.5Q;
+    const __float128 c = tgammaq(s) / 2;
+    return (float)powq(c, 1 / s);
+}
+
+int oracle_boys_approx_single(const double *x, int64_t count, const double *rec, int reclen,
+                              float *out, int64_t ld)
+{
+    record r;
+    if (parse_record(rec, reclen, &r) || count < 0 || ld < count)
+        return 1;
+    const int n = r.n;
+    const float kappa = oracle_kappa32(n);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < count; ++i) {
+        const double xi = x[i];
+        float *F = out + i;
+        if (!(xi >= 0)) {
+            for (int m = 0; m <= n; ++m)
+                F[(int64_t)m * ld] = NAN;
+            continue;
+        }
+        if (isinf(xi)) {
+            for (int m = 0; m <= n; ++m)
+                F[(int64_t)m * ld] = 0.0f;
+            continue;
+        }
+        if (xi > r.z) {
+            const double ix = 1.0 / xi;
+            double f = r.c0 / sqrt(xi);
+            F[0] = (float)f;
+            for (int m = 1; m <= n; ++m) {
+                f = f * (m - 0.5) * ix;
+                F[(int64_t)m * ld] = (float)f;
+            }
+            continue;
+        }
+        const float xf = (float)xi;
+        const float e = (float)exp_rn(-xi);
+        const float u = factors_f(xf, r.ug, r.pug, r.uq, r.puq, r.ul, r.pul);
+        const float v = factors_f(xf, r.vg, r.pvg, r.vq, r.pvq, r.vl, r.pvl);
+        const float Q = (float)r.q0 + (float)r.q1 * xf + (float)r.q2 * (u / v) * xf * xf;
+        const float W = powi_f(Q, n) * sqrtf(Q) * e;
+        const float G = xf + W;
+        const float t = kappa / G;
+        float Fm = powi_f(t, n) * sqrtf(t);
+        F[(int64_t)n * ld] = Fm;
+        for (int m = n; m >= 1; --m) {
+            Fm = (2.0f * xf * Fm + e) * (1.0f / (float)(2 * m - 1));
+            F[(int64_t)(m - 1) * ld] = Fm;
+        }
+    }
+    return 0;
+}
+
 /* 4. F~_n in binary128 from double-double coefficients                             */
 /*
  * recx[] layout: [0] n, then pairs (hi, lo) for q0, q1, q2, then for u and then v:

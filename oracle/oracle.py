@@ -13,6 +13,7 @@ exact_one(x, m)           the same for one order m, arrays of shape (len(x),).
 approx_f64(x, n)          the binary64 approximant (Eqs. fq, pqz, pz, qz, r, limf1),
                           shape (n+1, len(x)), float64.
 approx_mixed(x, n)        the mixed binary32/binary64 class, shape (n+1, len(x)), float32.
+approx_single(x, n)       the all-binary32 evaluation (Table 1's binary32 arithmetic), float32.
 approx_f32x(x, n)         the binary32-output class computed in binary64 (the ~28-bit
                           approximant, each value rounded once), shape (n+1, len(x)), float32.
 approx_split(x, n, nbar)  the two-approximation option: rows 0..nbar of approx_f64(x, nbar)
@@ -65,6 +66,10 @@ def lib():
         L.oracle_boys_approx_mixed.argtypes = [dp, i64, dp, ctypes.c_int, fp, i64]
         L.oracle_boys_approx_f64r.argtypes = [dp, i64, dp, ctypes.c_int, dp, i64]
         L.oracle_boys_approx_f64r.restype = ctypes.c_int
+        L.oracle_boys_approx_single.argtypes = [dp, i64, dp, ctypes.c_int, fp, i64]
+        L.oracle_boys_approx_single.restype = ctypes.c_int
+        L.oracle_kappa32.argtypes = [ctypes.c_int]
+        L.oracle_kappa32.restype = ctypes.c_float
         L.oracle_boys_approx_q.argtypes = [dp, i64, dp, dp, dp]
         L.oracle_exp_neg.argtypes = [dp, i64, dp]
         ip = ctypes.POINTER(ctypes.c_int32)
@@ -259,6 +264,24 @@ def approx_mixed(x, n: int, rec: Record | None = None):
     if rc:
         raise ValueError("oracle_boys_approx_mixed rejected its arguments")
     return out
+
+
+def approx_single(x, n: int, rec: Record | None = None):
+    """The all-binary32 evaluation of the binary32 sets (the arithmetic of Table 1's
+    binary32 columns), float32 (n+1, len(x))."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    r = rec if rec is not None else record("fp32", n)
+    fr = flat_record(r)
+    out = np.empty((n + 1, x.size), dtype=np.float32)
+    rc = lib().oracle_boys_approx_single(_dp(x), x.size, _dp(fr), fr.size, _fp(out), x.size)
+    if rc:
+        raise ValueError("oracle_boys_approx_single rejected its arguments")
+    return out
+
+
+def kappa32(n: int) -> float:
+    """c_n^(1/(n+1/2)) rounded to binary32, as the oracle computes it."""
+    return float(lib().oracle_kappa32(n))
 
 
 def approx_f32x(x, n: int, rec: Record | None = None):

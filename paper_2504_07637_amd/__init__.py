@@ -8,17 +8,18 @@ allocates tensors with PyTorch, takes the current HIP stream and marshals argume
     F = boys.boys_eval(x, 16)                  # (17, 2^20) float64, F[m, i] = F_m(x[i])
     G = boys.boys_eval(x, 16, precision="fp32")  # mixed class, float32 output
     H = boys.boys_eval(x, 16, precision="fp32x")  # float32 output at full single accuracy
+    S = boys.boys_eval(x, 16, precision="fp32s")  # all-binary32 arithmetic
 """
 from __future__ import annotations
 
 import ctypes
 
 from . import _lib
-from ._lib import FP32, FP32X, FP64, FP64_PLUS, BoysArray, BoysError, BoysTuning
+from ._lib import FP32, FP32S, FP32X, FP64, FP64_PLUS, BoysArray, BoysError, BoysTuning
 
 __all__ = ["boys_eval", "boys_eval_split", "boys_eri_ssss", "boys_eval_batched", "Plan", "autotune", "max_nmax", "cutoff",
            "precision_code", "padded_ld", "empty_out", "BoysError", "FP64", "FP32", "FP64_PLUS",
-           "FP32X"]
+           "FP32X", "FP32S"]
 
 
 def precision_code(precision) -> int:
@@ -30,6 +31,8 @@ def precision_code(precision) -> int:
         return FP64_PLUS
     if precision in (FP32X, "fp32x"):
         return FP32X
+    if precision in (FP32S, "fp32s", "single"):
+        return FP32S
     raise ValueError(f"unknown precision {precision!r}")
 
 
@@ -40,7 +43,7 @@ def _torch():
 
 def _out_dtype(code):
     torch = _torch()
-    return torch.float32 if code in (FP32, FP32X) else torch.float64
+    return torch.float32 if code in (FP32, FP32X, FP32S) else torch.float64
 
 
 def _stream_ptr(stream, device):
@@ -80,7 +83,7 @@ def padded_ld(n: int, precision) -> int:
 
     Rows that straddle cache lines are written as partial lines, which costs up to a
     third of the store bandwidth (measured); outputs allocated here use this stride."""
-    q = 32 if precision_code(precision) in (FP32, FP32X) else 16
+    q = 32 if precision_code(precision) in (FP32, FP32X, FP32S) else 16
     return max(q, (n + q - 1) // q * q)
 
 

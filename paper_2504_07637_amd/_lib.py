@@ -15,6 +15,7 @@ FP64 = 0
 FP32 = 1
 FP64_PLUS = 2
 FP32X = 3
+FP32S = 4
 
 OK = 0
 ERR_INVALID_ARGUMENT = 1

@@ -25,7 +25,7 @@ INCLUDE = os.path.join(REPO, "include")
 LIB = os.path.join(PKG, "libboys.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-CLASSES = (0, 1, 2, 3)          # boys_precision values
+CLASSES = (0, 1, 2, 3, 4)       # boys_precision values
 BUCKETS = 5                     # n_max buckets of the batched kernels
 # (schedule, K): persistent; one workgroup per tile of K * block; one wave per tile of K * 64
 SHAPES = ((0, 0), (1, 1), (1, 2), (1, 4), (2, 4))

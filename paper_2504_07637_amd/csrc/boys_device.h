@@ -524,4 +524,40 @@ __host__ __device__ __forceinline__ void eval_f32(double x, const double2 *__res
     }
 }
 
+// ---------------------------------------------------------------------------------
+// F_0..F_N for one argument, all binary32 below the cut-off (the arithmetic of Table 1's
+// binary32 columns): G = x + W in binary32 and F_N = (kappa_N / G)^(N+1/2) with kappa_N =
+// c_N^(1/(N+1/2)) in binary32 (c_N itself leaves the binary32 range beyond N = 27); the
+// recursion by reciprocals; past the cut-off the same long-range limit as eval_f32
+
+template <int N>
+__host__ __device__ __forceinline__ void eval_f32s(double x, const double2 *__restrict__ tab,
+                                                   float (&F)[N + 1])
+{
+    using S = boys_tab::F32Set<N>;
+    x = x >= 0.0 ? x : __builtin_nan("");  // as in eval_f64_set
+    if (!(x > S::z)) {
+        const float xf = (float)x;
+        const float e = (float)exp_rn(__builtin_fmax(-x, -120.0), tab);
+        const float u = factors<float, S::ug_n, S::uq_n, S::ul_n>(xf, S::ug, S::uq, S::ul);
+        const float v = factors<float, S::vg_n, S::vq_n, S::vl_n>(xf, S::vg, S::vq, S::vl);
+        const float Q = S::q0 + S::q1 * xf + S::q2 * (u / v) * xf * xf;
+        const float W = powi<N>(Q) * __builtin_sqrtf(Q) * e;
+        const float G = xf + W;
+        const float t = boys_tab::kKappa32[N] / G;
+        const float f = powi<N>(t) * __builtin_sqrtf(t);
+        F[N] = f;
+        recurse_down_rcp<N, float>(2.0f * xf, e, f, F);
+    } else {
+        const double ix = 1.0 / x;
+        double f = boys_tab::kC0 / __builtin_sqrt(x);
+        F[0] = (float)f;
+#pragma unroll
+        for (int m = 1; m <= N; ++m) {
+            f = f * (m - 0.5) * ix;
+            F[m] = (float)f;
+        }
+    }
+}
+
 }  // namespace boys

@@ -127,6 +127,16 @@ __device__ __forceinline__ void body_f32(const double *__restrict__ x, float *__
     store_rows<N>(F, out + i, ld);
 }
 
+// all binary32 below the cut-off (Table 1's binary32 arithmetic)
+template <int N>
+__device__ __forceinline__ void body_f32s(const double *__restrict__ x, float *__restrict__ out,
+                                          int64_t ld, int64_t i, const double2 *tab)
+{
+    float F[N + 1];
+    boys::eval_f32s<N>(__builtin_nontemporal_load(x + i), tab, F);
+    store_rows<N>(F, out + i, ld);
+}
+
 constexpr int cmin(int a, int b)
 {
     return a < b ? a : b;
@@ -136,15 +146,17 @@ constexpr int cmin(int a, int b)
 template <int C>
 constexpr int plain_block()
 {
-    return C == BOYS_FP32 || C == BOYS_FP32X ? 512 : 128;
+    return C == BOYS_FP32 || C == BOYS_FP32X || C == BOYS_FP32_SINGLE ? 512 : 128;
 }
 
 // largest order of a class
 template <int C>
 constexpr int class_max()
 {
-    return C == BOYS_FP32 ? kMaxN32 : C == BOYS_FP64 ? kMaxN64 : C == BOYS_FP32X ? kMaxN32x
-                                                                            : kMaxN64 - 1;
+    return C == BOYS_FP32 || C == BOYS_FP32_SINGLE ? kMaxN32
+           : C == BOYS_FP64                       ? kMaxN64
+           : C == BOYS_FP32X                      ? kMaxN32x
+                                                  : kMaxN64 - 1;
 }
 
 template <int C, int N>
@@ -156,6 +168,8 @@ __device__ __forceinline__ void body(const Desc &d, int64_t i, const double2 *ta
         body_f64plus<N>(d.x, static_cast<double *>(d.out), d.ld, i, tab);
     else if constexpr (C == BOYS_FP32X)
         body_f32x<N>(d.x, static_cast<float *>(d.out), d.ld, i, tab);
+    else if constexpr (C == BOYS_FP32_SINGLE)
+        body_f32s<N>(d.x, static_cast<float *>(d.out), d.ld, i, tab);
     else
         body_f32<N>(d.x, static_cast<float *>(d.out), d.ld, i, tab);
 }
@@ -188,7 +202,7 @@ __global__ __launch_bounds__(plain_block<C>()) void k_plain(const double *__rest
 {
     constexpr int BS = plain_block<C>();
     const double2 *tab;
-    if constexpr (C != BOYS_FP32 && C != BOYS_FP32X) {
+    if constexpr (C != BOYS_FP32 && C != BOYS_FP32X && C != BOYS_FP32_SINGLE) {
         tab = reinterpret_cast<const double2 *>(boys_tab::kExp2Tab);
     } else {
         __shared__ double2 lds_tab[256];
@@ -205,6 +219,8 @@ __global__ __launch_bounds__(plain_block<C>()) void k_plain(const double *__rest
             body_f64plus<N>(x, static_cast<double *>(out), ld, i, tab);
         else if constexpr (C == BOYS_FP32X)
             body_f32x<N>(x, static_cast<float *>(out), ld, i, tab);
+        else if constexpr (C == BOYS_FP32_SINGLE)
+            body_f32s<N>(x, static_cast<float *>(out), ld, i, tab);
         else
             body_f32<N>(x, static_cast<float *>(out), ld, i, tab);
     }
@@ -285,6 +301,9 @@ __device__ __forceinline__ void dispatch_class(int prec, int n, const Desc &d, i
         dispatch<BOYS_FP32, cmin(MAXN, class_max<BOYS_FP32>()), S, K>(n, d, start, cnt);
     else if (prec == BOYS_FP32X)
         dispatch<BOYS_FP32X, cmin(MAXN, class_max<BOYS_FP32X>()), S, K>(n, d, start, cnt);
+    else if (prec == BOYS_FP32_SINGLE)
+        dispatch<BOYS_FP32_SINGLE, cmin(MAXN, class_max<BOYS_FP32_SINGLE>()), S, K>(n, d, start,
+                                                                                     cnt);
     else
         dispatch<BOYS_FP64_PLUS, cmin(MAXN, class_max<BOYS_FP64_PLUS>()), S, K>(n, d, start,
                                                                                  cnt);

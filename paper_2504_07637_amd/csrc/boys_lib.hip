@@ -67,6 +67,8 @@ PlainLaunch plain_launcher(int32_t prec, int n)
         return boys_internal::plain_launcher<BOYS_FP64_PLUS>(n);
     case BOYS_FP32X:
         return boys_internal::plain_launcher<BOYS_FP32X>(n);
+    case BOYS_FP32_SINGLE:
+        return boys_internal::plain_launcher<BOYS_FP32_SINGLE>(n);
     }
     return nullptr;
 }
@@ -81,12 +83,14 @@ int max_nmax(int32_t prec)
         return kMaxN64 - 1;
     if (prec == BOYS_FP32X)
         return kMaxN32x;
+    if (prec == BOYS_FP32_SINGLE)
+        return kMaxN32;
     return -1;
 }
 
 int elem_bytes(int32_t prec)
 {
-    return prec == BOYS_FP32 || prec == BOYS_FP32X ? 4 : 8;
+    return prec == BOYS_FP32 || prec == BOYS_FP32X || prec == BOYS_FP32_SINGLE ? 4 : 8;
 }
 
 boys_status check_array(const double *x, int64_t n, int32_t n_max, const void *out,
@@ -572,6 +576,8 @@ double boys_cutoff(int32_t n, int32_t precision)
         return boys_tab::kCut64[n + 1];
     if (precision == BOYS_FP32X && n >= 0 && n <= kMaxN32x)
         return boys_tab::kCut32x[n];
+    if (precision == BOYS_FP32_SINGLE && n >= 0 && n <= kMaxN32)
+        return boys_tab::kCut32[n];
     return NAN;
 }
 

@@ -7,8 +7,9 @@ The header holds, as hexadecimal floating-point literals:
   * the binary64 sets once more as one runtime-indexed table (RtSet headers and one
     flat coefficient array), for the two-approximation option whose lower order is a
     launch argument;
-  * c_0 = sqrt(pi)/2 for the long-range limit past the cut-off (Eq. limf1), and
-    2 pi^(5/2) for the (ss|ss) integrals of the consumer kernel;
+  * c_0 = sqrt(pi)/2 for the long-range limit past the cut-off (Eq. limf1),
+    2 pi^(5/2) for the (ss|ss) integrals of the consumer kernel, and kappa_n =
+    c_n^(1/(n+1/2)) in binary32 for the all-binary32 class;
   * the tables of the correctly rounded exponential: 2^(j/256) for j = 0..255 as
     double-double pairs, and ln2/256 split into three parts for an exact reduction.
 
@@ -187,6 +188,14 @@ def main(dataset=DATASET, out=OUT):
     mp.mp.prec = 300
     lines.append(f"constexpr double kTwoPi52 = {float.hex(float(2 * mp.pi ** 2.5))};"
                  "  // 2 pi^(5/2), the (ss|ss) prefactor")
+    # kappa_n = c_n^(1/(n+1/2)) rounded once to binary32: F_n = (kappa_n / G)^(n+1/2)
+    # keeps the all-binary32 class in range (c_n itself exceeds binary32 beyond n = 27)
+    import numpy as np
+    kap = []
+    for n in range(max32 + 1):
+        c = mp.gamma(n + mp.mpf(1) / 2) / 2
+        kap.append(float(np.float32(float(c ** (1 / (n + mp.mpf(1) / 2))))))
+    lines.append("constexpr float kKappa32[] = {" + ", ".join(float.hex(v) + "f" for v in kap) + "};")
     lines.append("// exp(a) = 2^m 2^(j/256) exp(r), a = k ln2/256 + r, k = 256 m + j")
     lines.append(f"constexpr double kInvLn2x256 = {float.hex(inv)};")
     lines.append(f"constexpr double kLn2d256_1 = {float.hex(L1)};  // 36 significant bits")

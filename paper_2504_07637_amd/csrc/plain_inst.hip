@@ -18,7 +18,8 @@ hipError_t launch_plain(const double *x, int64_t n, void *out, int64_t ld, hipSt
 {
     constexpr int kBlock = plain_block<C>();
     constexpr int64_t kChunk = (int64_t)INT32_MAX / kBlock * kBlock;  // one grid's worth
-    using T = std::conditional_t<C == BOYS_FP32 || C == BOYS_FP32X, float, double>;
+    using T = std::conditional_t<C == BOYS_FP32 || C == BOYS_FP32X || C == BOYS_FP32_SINGLE,
+                                 float, double>;
     for (int64_t off = 0; off < n; off += kChunk) {
         const int64_t cnt = std::min(kChunk, n - off);
         const int grid = (int)((cnt + kBlock - 1) / kBlock);

@@ -122,10 +122,10 @@ struct Request {
 };
 
 // precision classes: 0 binary64, 1 mixed (binary32 output), 2 binary64 (order n+1 trick),
-// 3 binary32 output computed in binary64
+// 3 binary32 output computed in binary64, 4 all binary32
 inline uint64_t elem_size(int32_t prec)
 {
-    return prec == 1 || prec == 3 ? 4u : 8u;
+    return prec == 1 || prec == 3 || prec == 4 ? 4u : 8u;
 }
 
 // row stride of a request's output: every row starts on a 128-byte boundary
@@ -169,7 +169,7 @@ class Core {
     int submit(int64_t n, int32_t n_max, int32_t prec, const double *x_host, double now,
                uint64_t *id)
     {
-        if (n <= 0 || n_max < 0 || prec < 0 || prec > 3 || x_host == nullptr)
+        if (n <= 0 || n_max < 0 || prec < 0 || prec > 4 || x_host == nullptr)
             return 1;
         const uint64_t fp = footprint(n, n_max, prec);
         const int64_t tiles = (n + ex_->tile_args() - 1) / ex_->tile_args();

@@ -71,7 +71,7 @@ class Server:
         """A device copy of a completed request's output, shape (n_max+1, n)."""
         import torch
         _, n, n_max, code = self._live[rid]
-        dt = torch.float32 if code in (_lib.FP32, _lib.FP32X) else torch.float64
+        dt = torch.float32 if code in (_lib.FP32, _lib.FP32X, _lib.FP32S) else torch.float64
         out = torch.empty((n_max + 1, n), dtype=dt, device=self.device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)

@@ -34,7 +34,7 @@ int main()
         t[i] = now;
         len[i] = (int64_t)std::llround(std::exp(u(g)));
         nm[i] = (int)(g() % 21);
-        pr[i] = (int)(g() % 4);
+        pr[i] = (int)(g() % 5);
     }
     int64_t mu = 0;
     int mi = 0, mc = 0, nb = 0;

@@ -45,7 +45,7 @@ def test_argument_errors_are_reported_before_any_launch():
     assert lib.boys_eval(fake, 10, 4, fake, 9, L.FP64, None) == L.ERR_INVALID_ARGUMENT
     assert lib.boys_eval(fake, -1, 4, fake, 10, L.FP64, None) == L.ERR_INVALID_ARGUMENT
     assert lib.boys_eval(fake, 10, 4, fake, 10, 7, None) == L.ERR_INVALID_ARGUMENT
-    assert lib.boys_eval(fake, 10, 4, fake, 10, 4, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eval(fake, 10, 4, fake, 10, 5, None) == L.ERR_INVALID_ARGUMENT
     assert lib.boys_eval(fake, 10, -1, fake, 10, L.FP64, None) == L.ERR_UNSUPPORTED_NMAX
     big = lib.boys_max_nmax(L.FP64) + 1
     assert lib.boys_eval(fake, 10, big, fake, 10, L.FP64, None) == L.ERR_UNSUPPORTED_NMAX
@@ -102,7 +102,10 @@ def test_queries():
     assert lib.boys_max_nmax(L.FP64) == 36 and lib.boys_max_nmax(L.FP32) == 36
     assert lib.boys_max_nmax(L.FP64_PLUS) == 35
     assert lib.boys_max_nmax(L.FP32X) == 36
-    assert lib.boys_max_nmax(9) == -1 and lib.boys_max_nmax(4) == -1
+    assert lib.boys_max_nmax(L.FP32S) == 36
+    assert lib.boys_max_nmax(9) == -1 and lib.boys_max_nmax(5) == -1
+    for n in (0, 16, 36):
+        assert lib.boys_cutoff(n, L.FP32S) == lib.boys_cutoff(n, L.FP32)
     for n in (0, 16, 36):
         # z_{n,24} < z_{n,28} < z_{n,53}
         assert lib.boys_cutoff(n, L.FP32) < lib.boys_cutoff(n, L.FP32X) < lib.boys_cutoff(n, L.FP64)

@@ -14,17 +14,18 @@ def test_precision_names():
     for names, code in ((("fp64", "float64", "double", 0), _lib.FP64),
                         (("fp32", "float32", "mixed", 1), _lib.FP32),
                         (("fp64plus", "fp64+", 2), _lib.FP64_PLUS),
-                        (("fp32x", 3), _lib.FP32X)):
+                        (("fp32x", 3), _lib.FP32X),
+                        (("fp32s", "single", 4), _lib.FP32S)):
         for nm in names:
             assert boys.precision_code(nm) == code
-    for bad in ("fp16", 4, -1, None):
+    for bad in ("fp16", 5, -1, None):
         with pytest.raises(ValueError):
             boys.precision_code(bad)
 
 
 def test_padded_row_stride_is_whole_cache_lines():
     for n in (0, 1, 15, 16, 17, 31, 33, 1000, 65536):
-        for prec, es in (("fp64", 8), ("fp64plus", 8), ("fp32", 4), ("fp32x", 4)):
+        for prec, es in (("fp64", 8), ("fp64plus", 8), ("fp32", 4), ("fp32x", 4), ("fp32s", 4)):
             ld = boys.padded_ld(n, prec)
             assert ld >= max(n, 1) and (ld * es) % 128 == 0 and ld * es - n * es < 128 + 128
 

@@ -115,9 +115,9 @@ def test_every_schedule_equals_solo(tuning):
     import paper_2504_07637_amd as boys
     xs, hs, nm, pr = _batch(torch, 300, 70, nmax_hi=35)
     # every third array in the binary64 class with the order n+1 option, every fifth
-    # in the binary32-output class computed in binary64
-    pr = ["fp64plus" if k % 3 == 0 else "fp32x" if k % 5 == 0 else p
-          for k, p in enumerate(pr)]
+    # in the binary32-output class computed in binary64, every seventh all in binary32
+    pr = ["fp64plus" if k % 3 == 0 else "fp32x" if k % 5 == 0 else "fp32s" if k % 7 == 0
+          else p for k, p in enumerate(pr)]
     _say(f"[schedule] {tuning}")
     plan = boys.Plan(xs, nm, pr, tuning=tuning)
     plan.execute()

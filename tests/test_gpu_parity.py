@@ -42,7 +42,7 @@ def _special():
 def _gpu_eval(torch, x, n, prec, ld_pad=0):
     import paper_2504_07637_amd as boys
     xd = torch.from_numpy(x).to("cuda")
-    dt = torch.float32 if prec in ("fp32", "fp32x") else torch.float64
+    dt = torch.float32 if prec in ("fp32", "fp32x", "fp32s") else torch.float64
     if ld_pad:
         buf = torch.full((n + 1, x.size + ld_pad), -7.0, dtype=dt, device="cuda")
         out = buf[:, : x.size]
@@ -69,11 +69,13 @@ def _oracle(x, n, prec):
         return orc.approx_mixed(x, n)
     if prec == "fp32x":
         return orc.approx_f32x(x, n)
+    if prec == "fp32s":
+        return orc.approx_single(x, n)
     # the order n+1 option: the oracle's order n+1 evaluation without its top row
     return orc.approx_f64(x, n + 1)[: n + 1]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64plus", "fp32x"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64plus", "fp32x", "fp32s"])
 def test_identical_to_the_oracle_every_nmax(prec):
     torch = require_gpu()
     import paper_2504_07637_amd as boys
@@ -153,7 +155,7 @@ def test_error_against_exact_function_within_table1(prec, n, table1):
 def test_ragged_lengths_and_padded_rows(n):
     torch = require_gpu()
     x = inputs.integral_args(n, seed=n)
-    for prec in ("fp64", "fp32", "fp64plus", "fp32x"):
+    for prec in ("fp64", "fp32", "fp64plus", "fp32x", "fp32s"):
         _say(f"[ragged] {prec} n={n}")
         got = _gpu_eval(torch, x, 7, prec, ld_pad=37)
         assert same_bits(got, _oracle(x, 7, prec)).all()
@@ -242,7 +244,7 @@ def test_full_size_integral_workload_sampled():
                                     g.integers(0, n_args, 1 << 17)]))
     xd = torch.from_numpy(x).to("cuda")
     ti = torch.from_numpy(idx).to("cuda")
-    for prec in ("fp64", "fp32", "fp32x", "fp64plus", "split8"):
+    for prec in ("fp64", "fp32", "fp32x", "fp32s", "fp64plus", "split8"):
         _say(f"[full] {prec} n_max=16 count={n_args}")
         if prec == "split8":
             out = boys.boys_eval_split(xd, 16, 8)

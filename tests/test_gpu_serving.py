@@ -28,9 +28,10 @@ def test_serving_results_equal_solo(budget_mb, streams):
     P = pool.numel()
     reqs = inputs.serving_requests(rate=20000.0, duration=0.15, seed=55)
     # every fourth request in the order n+1 option or the binary32-output class computed
-    # in binary64, so all four classes share the batches
-    reqs = [(t, ln, nm, (2 if pr == 0 else 3) if i % 4 == 0 else pr)
-            for i, (t, ln, nm, pr) in enumerate(reqs)]
+    # in binary64, and some mixed-class requests all in binary32, so all five classes share
+    # the batches
+    reqs = [(t, ln, nm, (2 if pr == 0 else 3) if i % 4 == 0 else 4 if i % 4 == 2 and pr == 1
+             else pr) for i, (t, ln, nm, pr) in enumerate(reqs)]
     checked = []
     bad = []
     srv = None

@@ -53,6 +53,38 @@ def test_mixed_class_at_least_the_binary32_columns(n, table1):
         assert v >= want[key] - 1.0, (n, key, v, want[key])
 
 
+def test_kappa_is_the_rounded_root_of_c_n():
+    # F_n = c_n / G^(n+1/2) = (kappa_n / G)^(n+1/2): kappa_n = c_n^(1/(n+1/2)), c_n =
+    # Gamma(n+1/2)/2 (the x -> inf limit of Eq. fn), rounded once to binary32; checked at
+    # 50 digits against both neighbouring binary32 values
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 50
+    for n in NS:
+        s = mpmath.mpf(n) + mpmath.mpf(1) / 2
+        exact = (mpmath.gamma(s) / 2) ** (1 / s)
+        k = np.float32(orc.kappa32(n))
+        lo, hi = np.nextafter(k, np.float32(0)), np.nextafter(k, np.float32(np.inf))
+        d = abs(mpmath.mpf(float(k)) - exact)
+        assert d <= abs(mpmath.mpf(float(lo)) - exact) and d <= abs(mpmath.mpf(float(hi)) - exact), n
+
+
+@pytest.mark.parametrize("n", NS)
+def test_all_binary32_evaluation_matches_table1(n, table1):
+    # Table 1's binary32 columns are all-binary32 arithmetic: the oracle's evaluation of the
+    # binary32 sets in binary32 (F_n = (kappa_n / G)^(n+1/2)) lands within one bit of them
+    r = orc.record("fp32", n)
+    x = np.arange(GRID) * (r["z"] / GRID)
+    A = orc.approx_single(x, n).astype(np.float64)
+    want = table1[n]["fp32"]
+    for key, m in (("eb0", 0), ("ebn1", n - 1), ("ebn", n)):
+        if m < 0 or want[key] is None:
+            continue
+        hi, lo = orc.exact_one(x, m)
+        ok = np.abs(hi) >= 1.1754943508222875e-38
+        got = orc.bits(orc.rel_err(A[m][ok], hi[ok], lo[ok]))
+        assert abs(got - want[key]) <= 1.0, (n, key, got, want[key])
+
+
 def test_value_at_zero():
     # F~_m(0) must be 1/(2m+1) to the accuracy of the approximant
     for n in (0, 5, 16, 36):
@@ -66,6 +98,9 @@ def test_special_inputs():
     for n in (0, 9):
         F = orc.approx_f64(x, n)
         G = orc.approx_mixed(x, n)
+        H = orc.approx_single(x, n)
+        assert np.all(np.isnan(H[:, :2])) and np.all(H[:, 2] == 0)
+        assert np.array_equal(H[:, 3], H[:, 4])
         assert np.all(np.isnan(F[:, :2])) and np.all(np.isnan(G[:, :2]))
         assert np.all(F[:, 2] == 0) and np.all(G[:, 2] == 0)
         assert np.array_equal(F[:, 3], F[:, 4]) and np.array_equal(G[:, 3], G[:, 4])

@@ -36,7 +36,7 @@ def harness(tmp_path_factory):
 
 def footprint(n, nmax, prec):
     a = lambda v: (v + 255) // 256 * 256
-    es = 4 if prec in (1, 3) else 8   # binary32 outputs for classes 1 and 3
+    es = 4 if prec in (1, 3, 4) else 8   # binary32 outputs for classes 1, 3 and 4
     q = 128 // es
     ld = (n + q - 1) // q * q
     return a(8 * n) + a((nmax + 1) * ld * es)
@@ -67,7 +67,7 @@ def _poisson(seed, count, rate, lo=64, hi=262144, nmax_hi=20):
     t = np.cumsum(g.exponential(1.0 / rate, count))
     ln = np.rint(np.exp(g.uniform(np.log(lo), np.log(hi), count))).astype(np.int64)
     nm = g.integers(0, nmax_hi + 1, count).astype(np.int32)
-    pr = g.integers(0, 4, count).astype(np.int32)
+    pr = g.integers(0, 5, count).astype(np.int32)
     return t, ln, nm, pr
 
 
@@ -117,7 +117,7 @@ def test_oversized_requests_are_refused(harness):
     assert list(r["rc"]) == [0, 3, 0]
     assert r["done"] == 2
     # an unknown precision class is an argument error (1), the others are admitted
-    pr = np.array([4, 3, 2], dtype=np.int32)
+    pr = np.array([5, 4, 2], dtype=np.int32)
     ln = np.array([1000, 1000, 1000], dtype=np.int64)
     r = simulate(harness, t, ln, nm, pr, 1 << 30)
     assert list(r["rc"]) == [1, 0, 0] and r["done"] == 2
