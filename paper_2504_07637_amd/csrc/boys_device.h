@@ -22,7 +22,9 @@
 //   * exp(-x) is the correctly rounded binary64 value (Tang's table method with a
 //     double-only fast path and Ziv's rounding test; when the test cannot decide, a
 //     double-double evaluation with error below 2^-95 before its one rounding, so a
-//     misrounding needs exp(-x) within 2^-95 of a rounding boundary);
+//     misrounding needs exp(-x) within 2^-95 of a rounding boundary); the classes with
+//     binary32 arithmetic use that value rounded to binary32, which a shorter evaluation
+//     decides whenever it is safely away from a binary32 rounding midpoint (exp_rn32);
 //   * y^n is left-to-right binary powering, y^(n+1/2) = y^n * sqrt(y);
 //   * the recursion F_{m-1} = RN(RN(RN(2x) F_m) + e) / (2m-1)) divides by the odd
 //     constant d = 2m-1 as q = t*r, r = RN(1/d),
@@ -153,6 +155,37 @@ __host__ __device__ __forceinline__ double exp_rn(double a, const double2 *__res
     if (s.hi + e * 0x1.0001p+0 == s.hi)
         return __builtin_ldexp(s.hi, m);
     return exp_rn_slow(r, T, m);
+}
+
+// RN32(exp_rn(a)) for a in [-120, 0]: the binary32 rounding of the correctly rounded
+// binary64 exp, as the classes with binary32 arithmetic use it.  A short evaluation
+// usually decides it: v = T_hi * P(r), P the degree-4 Taylor polynomial of exp(r) (|r| <=
+// ln2/512, truncation below 2^-54.5), r from the two-part reduction, so that v differs
+// from exp(a) 2^-m by less than 2^-51 relative and from RN64(exp(a)) 2^-m by less than
+// 2^-50.9.
+// When v lies farther than 2^-47 (absolute, v < 2) from every binary32 rounding midpoint,
+// exp(a) and its binary64 rounding round to the same binary32 value as v.  Otherwise, or
+// when the result would fall below the binary32 normal range, the full exp_rn decides.
+__host__ __device__ __forceinline__ float exp_rn32(double a, const double2 *__restrict__ tab)
+{
+    using namespace boys_tab;
+    const double kd = __builtin_rint(a * kInvLn2x256);
+    const int k = (int)kd;
+    const int m = k >> 8;  // floor(k / 256)
+    double r = __builtin_fma(-kd, kLn2d256_1, a);
+    r = __builtin_fma(-kd, kLn2d256_2, r);
+    double P = __builtin_fma(r, kInvFact4_hi, kInvFact3_hi);
+    P = __builtin_fma(r, P, 0.5);
+    P = __builtin_fma(r, P, 1.0);
+    P = __builtin_fma(r, P, 1.0);
+    const double v = tab[k & 255].x * P;
+    const float f = (float)v;
+    const double d = v - (double)f;  // exact
+    // half a binary32 ulp below 1 and above it, less the error bound
+    const double h = v < 1.0 ? 0x1p-25 - 0x1p-47 : 0x1p-24 - 0x1p-47;
+    if (__builtin_fabs(d) < h && m >= -125)
+        return __builtin_ldexpf(f, m);
+    return (float)exp_rn(a, tab);
 }
 
 // ---------------------------------------------------------------------------------
@@ -503,7 +536,7 @@ __host__ __device__ __forceinline__ void eval_f32(double x, const double2 *__res
     x = x >= 0.0 ? x : __builtin_nan("");  // as in eval_f64_set
     if (!(x > S::z)) {
         const float xf = (float)x;
-        const float e = (float)exp_rn(__builtin_fmax(-x, -120.0), tab);
+        const float e = exp_rn32(__builtin_fmax(-x, -120.0), tab);
         const float u = factors<float, S::ug_n, S::uq_n, S::ul_n>(xf, S::ug, S::uq, S::ul);
         const float v = factors<float, S::vg_n, S::vq_n, S::vl_n>(xf, S::vg, S::vq, S::vl);
         const float Q = S::q0 + S::q1 * xf + S::q2 * (u / v) * xf * xf;
@@ -538,7 +571,7 @@ __host__ __device__ __forceinline__ void eval_f32s(double x, const double2 *__re
     x = x >= 0.0 ? x : __builtin_nan("");  // as in eval_f64_set
     if (!(x > S::z)) {
         const float xf = (float)x;
-        const float e = (float)exp_rn(__builtin_fmax(-x, -120.0), tab);
+        const float e = exp_rn32(__builtin_fmax(-x, -120.0), tab);
         const float u = factors<float, S::ug_n, S::uq_n, S::ul_n>(xf, S::ug, S::uq, S::ul);
         const float v = factors<float, S::vg_n, S::vq_n, S::vl_n>(xf, S::vg, S::vq, S::vl);
         const float Q = S::q0 + S::q1 * xf + S::q2 * (u / v) * xf * xf;

@@ -196,13 +196,29 @@ __device__ __forceinline__ unsigned block_index()
     return b;
 }
 
+// Where the plain kernel reads the exp table: the binary64 classes through L1; binary32
+// outputs computed in binary64 from a copy staged in LDS; the classes with binary32
+// arithmetic from LDS at orders 11..20 and through L1 otherwise (measured at 2^26
+// arguments, 512-thread workgroups: LDS 5-7% faster at n_max 12..18, L1 3-8% faster at
+// n_max <= 8 and 3-7% at n_max >= 22, the two even at 10 and 20).
+template <int C, int N>
+constexpr bool plain_lds_table()
+{
+    if constexpr (C == BOYS_FP32X)
+        return true;
+    else if constexpr (C == BOYS_FP32 || C == BOYS_FP32_SINGLE)
+        return N >= 11 && N <= 20;
+    else
+        return false;
+}
+
 template <int C, int N>
 __global__ __launch_bounds__(plain_block<C>()) void k_plain(const double *__restrict__ x, int64_t n,
                                                             void *__restrict__ out, int64_t ld)
 {
     constexpr int BS = plain_block<C>();
     const double2 *tab;
-    if constexpr (C != BOYS_FP32 && C != BOYS_FP32X && C != BOYS_FP32_SINGLE) {
+    if constexpr (!plain_lds_table<C, N>()) {
         tab = reinterpret_cast<const double2 *>(boys_tab::kExp2Tab);
     } else {
         __shared__ double2 lds_tab[256];

@@ -88,6 +88,29 @@ def test_identical_to_the_oracle_every_nmax(prec):
         assert not msg, msg
 
 
+def _exp_midpoint_args(count, seed):
+    # x with exp(-x) within a few binary64 ulps of a binary32 rounding midpoint (below the
+    # largest binary32 cut-off): the cases where the binary32 classes' exponential must
+    # tell RN32(RN64(exp(-x))) apart from a nearby rounding
+    g = np.random.default_rng(seed)
+    f = np.float32(np.exp(-g.uniform(0.0, 78.0, count))).astype(np.float64)
+    mid = f + np.spacing(f.astype(np.float32)).astype(np.float64) / 2
+    x = -np.log(mid)
+    x = np.concatenate([x, np.nextafter(x, 0.0), np.nextafter(x, np.inf)])
+    return x[x >= 0.0]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp32s"])
+def test_binary32_exp_rounding_near_midpoints(prec):
+    torch = require_gpu()
+    x = _exp_midpoint_args(1 << 16, 29)
+    for n in (0, 1, 4, 16, 36):
+        _say(f"[midpoint] {prec} n_max={n} count={x.size}")
+        got = _gpu_eval(torch, x, n, prec)
+        msg = report_mismatch(f"midpoint {prec} n_max={n}", got, _oracle(x, n, prec))
+        assert not msg, msg
+
+
 def _bounds(table1, cls, n):
     t = table1[n][cls]
     eb0, ebn1, ebn = t["eb0"], t["ebn1"], t["ebn"]
