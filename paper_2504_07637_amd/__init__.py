@@ -22,23 +22,31 @@ __all__ = ["boys_eval", "boys_eval_split", "boys_eri_ssss", "boys_eval_batched",
            "FP32X", "FP32S"]
 
 
+_CODES = {}
+for _code, _names in ((FP64, ("fp64", "float64", "double")), (FP32, ("fp32", "float32", "mixed")),
+                      (FP64_PLUS, ("fp64plus", "fp64+")), (FP32X, ("fp32x",)),
+                      (FP32S, ("fp32s", "single"))):
+    _CODES[_code] = _code
+    for _name in _names:
+        _CODES[_name] = _code
+
+
 def precision_code(precision) -> int:
-    if precision in (FP64, "fp64", "float64", "double"):
-        return FP64
-    if precision in (FP32, "fp32", "float32", "mixed"):
-        return FP32
-    if precision in (FP64_PLUS, "fp64plus", "fp64+"):
-        return FP64_PLUS
-    if precision in (FP32X, "fp32x"):
-        return FP32X
-    if precision in (FP32S, "fp32s", "single"):
-        return FP32S
-    raise ValueError(f"unknown precision {precision!r}")
+    try:
+        return _CODES[precision]
+    except (KeyError, TypeError):
+        raise ValueError(f"unknown precision {precision!r}") from None
+
+
+_TORCH = None
 
 
 def _torch():
-    import torch
-    return torch
+    global _TORCH
+    if _TORCH is None:
+        import torch
+        _TORCH = torch
+    return _TORCH
 
 
 def _out_dtype(code):
@@ -49,21 +57,36 @@ def _out_dtype(code):
 def _stream_ptr(stream, device):
     torch = _torch()
     if stream is None:
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        idx = device if isinstance(device, int) else device.index
+        if raw is not None and idx is not None:
+            return raw(idx)  # the current stream's handle, without building a Stream object
         stream = torch.cuda.current_stream(device)
-    return ctypes.c_void_p(stream.cuda_stream)
+    return stream.cuda_stream
+
+
+_SINGLE_DEVICE = None
+
+
+def _single_device():
+    global _SINGLE_DEVICE
+    if _SINGLE_DEVICE is None:
+        _SINGLE_DEVICE = _torch().cuda.device_count() == 1
+    return _SINGLE_DEVICE
 
 
 class _on_device:
-    """Make `device` current for the duration of a call (a no-op when it already is)."""
+    """Make `device` (a torch.device or an index) current for the duration of a call (a
+    no-op when it already is, and when only one device is visible)."""
 
     __slots__ = ("dev", "prev")
 
     def __init__(self, device):
-        self.dev = device.index  # None: the current device
+        self.dev = device if isinstance(device, int) else device.index  # None: current
         self.prev = None
 
     def __enter__(self):
-        if self.dev is None:
+        if self.dev is None or _single_device():
             return self
         torch = _torch()
         cur = torch.cuda.current_device()
@@ -108,22 +131,23 @@ def boys_eval(x, n_max: int, precision="fp64", out=None, stream=None):
 
     The row stride is out.stride(0); when out is not given it is padded so that every
     row starts on a 128-byte boundary (see padded_ld)."""
-    torch = _torch()
     _check_x(x)
     code = precision_code(precision)
     n = x.numel()
+    dev = x.get_device()
     if out is None:
         out = empty_out(n, n_max, code, x.device)
     else:
-        if out.dtype != _out_dtype(code) or out.device != x.device or out.dim() != 2:
+        if out.dtype != _out_dtype(code) or out.get_device() != dev or out.dim() != 2:
             raise TypeError("out has the wrong dtype, device or rank")
         if out.shape[0] != n_max + 1 or out.shape[1] != n or out.stride(1) != 1:
             raise ValueError("out must be (n_max+1, n) with unit column stride")
     ld = out.stride(0) if n > 0 else max(n, 1)
-    with _on_device(x.device):
+    with _on_device(dev):
         st = _lib.lib().boys_eval(x.data_ptr(), n, n_max, out.data_ptr(), ld, code,
-                                  _stream_ptr(stream, x.device))
-    _lib.check(st, "boys_eval")
+                                  _stream_ptr(stream, dev))
+    if st:
+        _lib.check(st, "boys_eval")
     return out
 
 

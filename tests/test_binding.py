@@ -35,6 +35,7 @@ def test_device_guard_switches_only_when_needed(monkeypatch):
 
     class FakeCuda:
         cur = 0
+        count = 4
 
         @staticmethod
         def current_device():
@@ -45,7 +46,12 @@ def test_device_guard_switches_only_when_needed(monkeypatch):
             calls.append(d)
             FakeCuda.cur = d
 
+        @staticmethod
+        def device_count():
+            return FakeCuda.count
+
     monkeypatch.setattr(boys, "_torch", lambda: types.SimpleNamespace(cuda=FakeCuda))
+    monkeypatch.setattr(boys, "_SINGLE_DEVICE", None)
     with boys._on_device(types.SimpleNamespace(index=0)):
         pass
     with boys._on_device(types.SimpleNamespace(index=None)):
@@ -54,6 +60,15 @@ def test_device_guard_switches_only_when_needed(monkeypatch):
     with boys._on_device(types.SimpleNamespace(index=2)):
         assert FakeCuda.cur == 2
     assert FakeCuda.cur == 0 and calls == [2, 0]
+    with boys._on_device(3):  # an index instead of a device
+        assert FakeCuda.cur == 3
+    assert FakeCuda.cur == 0 and calls == [2, 0, 3, 0]
+    # with one visible device there is nothing to switch
+    monkeypatch.setattr(boys, "_SINGLE_DEVICE", None)
+    FakeCuda.count, FakeCuda.cur = 1, 5
+    with boys._on_device(0):
+        assert FakeCuda.cur == 5
+    assert calls == [2, 0, 3, 0]
 
 
 def test_bench_refuses_more_than_one_gpu():
