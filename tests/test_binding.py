@@ -71,6 +71,29 @@ def test_device_guard_switches_only_when_needed(monkeypatch):
     assert calls == [2, 0, 3, 0]
 
 
+def test_stream_handle_with_and_without_the_raw_lookup(monkeypatch):
+    # the current stream's handle comes from torch's raw lookup when it exists, else from
+    # a Stream object; an explicit stream is used as given
+    class FakeStream:
+        def __init__(self, h):
+            self.cuda_stream = h
+
+    class FakeCuda:
+        @staticmethod
+        def current_stream(device):
+            return FakeStream(1000 + (device if isinstance(device, int) else 7))
+
+    raw = types.SimpleNamespace(_cuda_getCurrentRawStream=lambda idx: 2000 + idx)
+    monkeypatch.setattr(boys, "_torch", lambda: types.SimpleNamespace(cuda=FakeCuda, _C=raw))
+    assert boys._stream_ptr(None, 3) == 2003
+    assert boys._stream_ptr(None, types.SimpleNamespace(index=1)) == 2001
+    assert boys._stream_ptr(None, types.SimpleNamespace(index=None)) == 1007
+    assert boys._stream_ptr(FakeStream(55), 3) == 55
+    bare = types.SimpleNamespace()
+    monkeypatch.setattr(boys, "_torch", lambda: types.SimpleNamespace(cuda=FakeCuda, _C=bare))
+    assert boys._stream_ptr(None, 3) == 1003
+
+
 def test_bench_refuses_more_than_one_gpu():
     out = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], capture_output=True,
                          text=True, timeout=120)
