@@ -52,6 +52,22 @@ constexpr int kNumBuckets = 5;
 
 using boys_internal::Desc;
 
+// Every array the kernels read or write lives in global memory.  A pointer that reaches a
+// kernel through a descriptor in memory carries no address space, and the compiler would
+// access it with flat instructions (which also count against the LDS/scalar wait
+// counter); these access through a global-address-space pointer instead.
+template <typename T>
+__device__ __forceinline__ T load_nt(const T *p)
+{
+    return __builtin_nontemporal_load((const __attribute__((address_space(1))) T *)p);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_nt(T v, T *p)
+{
+    __builtin_nontemporal_store(v, (__attribute__((address_space(1))) T *)p);
+}
+
 // F_0..F_N of one argument to rows 0..N of the output (row stride ld), non-temporal.  The
 // address walks by ld: written as out + m*ld + i, the compiler forms each row address with
 // two 64-bit vector multiply-adds, which costs the VALU-bound classes measurably.
@@ -60,7 +76,7 @@ __device__ __forceinline__ void store_rows(const T *F, T *p, int64_t ld)
 {
 #pragma unroll
     for (int m = 0; m <= N; ++m) {
-        __builtin_nontemporal_store(F[m], p);
+        store_nt(F[m], p);
         p += ld;
     }
 }
@@ -71,7 +87,7 @@ __device__ __forceinline__ void store_rows_f32(const double *F, float *p, int64_
 {
 #pragma unroll
     for (int m = 0; m <= N; ++m) {
-        __builtin_nontemporal_store((float)F[m], p);
+        store_nt((float)F[m], p);
         p += ld;
     }
 }
@@ -88,7 +104,7 @@ __device__ __forceinline__ void body_f64(const double *__restrict__ x, double *_
                                          int64_t ld, int64_t i, const double2 *tab)
 {
     double F[N + 1];
-    boys::eval_f64<N>(__builtin_nontemporal_load(x + i), tab, F);
+    boys::eval_f64<N>(load_nt(x + i), tab, F);
     store_rows<N>(F, out + i, ld);
 }
 
@@ -99,7 +115,7 @@ __device__ __forceinline__ void body_f64plus(const double *__restrict__ x,
                                              const double2 *tab)
 {
     double F[N + 2];
-    boys::eval_f64<N + 1>(__builtin_nontemporal_load(x + i), tab, F);
+    boys::eval_f64<N + 1>(load_nt(x + i), tab, F);
     store_rows<N>(F, out + i, ld);
 }
 
@@ -110,7 +126,7 @@ __device__ __forceinline__ void body_f32x(const double *__restrict__ x, float *_
                                           int64_t ld, int64_t i, const double2 *tab)
 {
     double F[N + 1];
-    boys::eval_f32r<N>(__builtin_nontemporal_load(x + i), tab, F);
+    boys::eval_f32r<N>(load_nt(x + i), tab, F);
     store_rows_f32<N>(F, out + i, ld);
 }
 
@@ -123,7 +139,7 @@ __device__ __forceinline__ void body_f32(const double *__restrict__ x, float *__
                                          int64_t ld, int64_t i, const double2 *tab)
 {
     float F[N + 1];
-    boys::eval_f32<N>(__builtin_nontemporal_load(x + i), tab, F);
+    boys::eval_f32<N>(load_nt(x + i), tab, F);
     store_rows<N>(F, out + i, ld);
 }
 
@@ -133,7 +149,7 @@ __device__ __forceinline__ void body_f32s(const double *__restrict__ x, float *_
                                           int64_t ld, int64_t i, const double2 *tab)
 {
     float F[N + 1];
-    boys::eval_f32s<N>(__builtin_nontemporal_load(x + i), tab, F);
+    boys::eval_f32s<N>(load_nt(x + i), tab, F);
     store_rows<N>(F, out + i, ld);
 }
 
@@ -398,13 +414,13 @@ __global__ __launch_bounds__(128) void k_split(const double *__restrict__ x, int
     const int64_t i = (int64_t)block_index<xcd_contiguous<BOYS_FP64, N>()>() * 128 + threadIdx.x;
     if (i < n) {
         double F[N + 1];
-        boys::eval_split<N>(__builtin_nontemporal_load(x + i), nbar,
+        boys::eval_split<N>(load_nt(x + i), nbar,
                             reinterpret_cast<const double2 *>(boys_tab::kExp2Tab), F);
         // indexed row addresses here, not store_rows: with the pointer walk the compiler
         // turns the branches on nbar into selects (static VALU count 812 against 755)
 #pragma unroll
         for (int m = 0; m <= N; ++m)
-            __builtin_nontemporal_store(F[m], out + (int64_t)m * ld + i);
+            store_nt(F[m], out + (int64_t)m * ld + i);
     }
 }
 
@@ -430,7 +446,7 @@ __global__ __launch_bounds__(256) void k_eri_ssss(PairList bra, PairList ket, do
     boys::eri_ssss_one<N>(bra, ket, i, j, K, s_exp_tab, acc);
 #pragma unroll
     for (int m = 0; m <= N; ++m)
-        __builtin_nontemporal_store(acc[m], out + (int64_t)m * ld + ij);
+        store_nt(acc[m], out + (int64_t)m * ld + ij);
 }
 
 __global__ void k_reset(uint32_t *counter)
