@@ -295,6 +295,43 @@ def test_runs_on_a_side_stream():
     assert same_bits(out.cpu().numpy(), orc.approx_f64(x, 16)).all()
 
 
+def test_concurrent_calls_from_host_threads():
+    # the entry points are reentrant: four host threads, each on a stream of its own,
+    # call boys_eval repeatedly with different sizes, orders and classes; the last results
+    # of each equal the oracle bit for bit
+    torch = require_gpu()
+    import threading
+    import paper_2504_07637_amd as boys
+    jobs = [(inputs.integral_args(50_000 + 777 * k, seed=300 + k), n, p)
+            for k, (n, p) in enumerate([(4, "fp64"), (16, "fp32"), (36, "fp32s"), (9, "fp64plus")])]
+    results, errors = [None] * len(jobs), []
+
+    def work(k):
+        try:
+            x, n, p = jobs[k]
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                xd = torch.from_numpy(x).to("cuda")
+                outs = [boys.boys_eval(xd, n, p) for _ in range(8)]
+            s.synchronize()
+            results[k] = [o.cpu().numpy() for o in outs[-2:]]
+        except Exception as e:  # reported below, in the test's own thread
+            errors.append(e)
+
+    _say("[threads] 4 host threads x 8 calls")
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(len(jobs))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not errors, errors
+    for (x, n, p), got in zip(jobs, results):
+        want = _oracle(x, n, p)
+        for g in got:
+            msg = report_mismatch(f"thread {p} n_max={n}", g, want)
+            assert not msg, msg
+
+
 def test_arrays_longer_than_one_grid():
     # more than 2^31 arguments: the host splits the launch into grids of at most
     # INT32_MAX / block workgroups' worth; check the arguments around every split point
