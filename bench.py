@@ -100,10 +100,21 @@ def timed(torch, fn, steps, warmup):
     return wall, e0.elapsed_time(e1) / 1e3
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(x, target_s):
     from oracle import oracle as orc
-    threads = len(os.sched_getaffinity(0))
-    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
+    os.environ.setdefault("OMP_NUM_THREADS", str(len(os.sched_getaffinity(0))))
+    threads = int(os.environ["OMP_NUM_THREADS"])  # what the oracle's OpenMP loops use
     n = 1 << 18
     while True:
         t0 = time.perf_counter()
@@ -117,7 +128,7 @@ def cpu_baseline(x, target_s):
     orc.exact(x[:ne], N_MAX)
     dte = time.perf_counter() - t0
     return {"value": (N_MAX + 1) * n / dt, "unit": "values/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"first {n} arguments of the same 2^26 workload, n_max=16, binary64 "
                       f"approximant oracle (plain C, OpenMP, {dt:.2f} s)",
             "exact_oracle_values_per_s": (N_MAX + 1) * ne / dte,
