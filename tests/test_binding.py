@@ -1,5 +1,7 @@
 """Host-side logic of the Python binding and the benchmark (no device calls)."""
 import json
+import os
+import re
 import subprocess
 import sys
 import types
@@ -8,6 +10,8 @@ import pytest
 
 import paper_2504_07637_amd as boys
 from paper_2504_07637_amd import _lib
+
+REPO = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_precision_names():
@@ -92,6 +96,26 @@ def test_stream_handle_with_and_without_the_raw_lookup(monkeypatch):
     bare = types.SimpleNamespace()
     monkeypatch.setattr(boys, "_torch", lambda: types.SimpleNamespace(cuda=FakeCuda, _C=bare))
     assert boys._stream_ptr(None, 3) == 1003
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    # no CPU or PyTorch fallback: without libboys.so every entry point raises
+    from paper_2504_07637_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libboys.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.lib()
+
+
+def test_product_path_never_imports_the_oracle():
+    pkg = os.path.join(REPO, "paper_2504_07637_amd")
+    for root, _, files in os.walk(pkg):
+        if os.sep + "fit" in root:
+            continue  # the offline fitter is not on the evaluation path
+        for f in files:
+            if f.endswith(".py"):
+                text = open(os.path.join(root, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle\b", text, re.M), f
 
 
 def test_bench_refuses_more_than_one_gpu():
