@@ -114,9 +114,9 @@ boys_status boys_eval_split(const double *x, int64_t n, int32_t n_bar, int32_t n
  * with F_m the BOYS_FP64 evaluation of order n_max; a contracted pair sums over its
  * primitive pairs, bra primitives outer and ket primitives inner, in the order below:
  *     pq = p*q; spq = p+q; rho = pq/spq; d = P - Q; r2 = (dx*dx + dy*dy) + dz*dz;
- *     T = rho*r2; s = (w_a*w_b) * (K / (pq*sqrt(spq))); acc_m = acc_m + s*F_m(T),
- * K = 2 pi^(5/2) rounded to binary64.  Each output is a plain sequential sum, so results
- * are reproducible bit for bit.
+ *     T = rho*r2; s = (w_a*w_b) * (K / (pq*sqrt(spq))); acc_m = fma(s, F_m(T), acc_m),
+ * K = 2 pi^(5/2) rounded to binary64 and fma one correctly rounded multiply-add.  Each
+ * output is a plain sequential sum, so results are reproducible bit for bit.
  */
 typedef struct {
     const double *p;       /* device: exponent sums p of the primitive pairs            */

@@ -585,7 +585,7 @@ int oracle_eri_ssss(const double *rec, int reclen, const double *bra, int64_t ld
                 const double sc = (wa * wb) * (K / (pq * sqrt(spq)));
                 approx_one_d(&r, T, F, 1);
                 for (int m = 0; m <= n; ++m)
-                    acc[m] = acc[m] + sc * F[m];
+                    acc[m] = fma(sc, F[m], acc[m]);
             }
         }
         for (int m = 0; m <= n; ++m)

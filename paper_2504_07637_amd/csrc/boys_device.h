@@ -520,7 +520,7 @@ __host__ __device__ __forceinline__ void eri_ssss_one(const PairList &bra, const
             eval_f64<N>(T, tab, F);
 #pragma unroll
             for (int m = 0; m <= N; ++m)
-                acc[m] = acc[m] + s * F[m];
+                acc[m] = __builtin_fma(s, F[m], acc[m]);
         }
     }
 }
