@@ -312,6 +312,25 @@ def traffic_for(hash_now):
     return t.get("bytes_per_launch")
 
 
+def valu_for(hash_now, kernel, launch_s):
+    """The kernel's VALU use by counters (same profile file), while the sources match:
+    issue fraction of the 4-cycle capacity, VALUBusy, and executed binary64 FLOP/s
+    against the binary64 vector peak."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    v = (t.get("valu") or {}).get(kernel)
+    if t.get("kernel_hash") != hash_now or not v:
+        return None
+    tf = v["fp64_flops"] / launch_s / 1e12
+    return {"issue_fraction": v["issue_fraction_4cycle"], "valu_busy": v["valu_busy"],
+            "lane_instructions_per_argument": v["valu_wave_instructions"] * 64 / N_ARGS,
+            "fp64_tflops": tf, "fp64_peak_tflops": PEAK_FP64_TFLOPS,
+            "fp64_frac": tf / PEAK_FP64_TFLOPS}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -382,6 +401,7 @@ def main():
                    "n_args": N_ARGS, "n_max": N_MAX},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_for(khash),
+                     "valu": valu_for(khash, "k_plain<0, 16>", launch_s),
                      "kernel": "k_plain<FP64,16>", "launch_ms": launch_s * 1e3,
                      "alg_bytes_per_launch": alg_bytes, "kernel_hash": khash},
         "fp32": {"value": v32, "unit": "values/s", "ms_per_step": wall32 / args.steps * 1e3,
