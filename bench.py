@@ -225,12 +225,24 @@ def batched(torch, boys, inputs, steps):
     # the same arrays as 8,192 separate boys_eval calls into the plan's outputs
     solo = lambda: [boys.boys_eval(xi, m, p, out=o) for xi, m, p, o in zip(xs, nm, pr, plan.outs)]
     solo_wall, solo_gpu = timed(torch, solo, 2, 1)
+    # the same arguments grouped by (class, n_max), one plain launch per group: the plain
+    # kernels' time for this work, without per-array call overhead
+    groups = {}
+    for xi, m, p in zip(xs, nm, pr):
+        groups.setdefault((p, m), []).append(xi)
+    gx = [(torch.cat(v), m, p) for (p, m), v in sorted(groups.items())]
+    go = [boys.empty_out(xg.numel(), m, p) for xg, m, p in gx]
+    grouped = lambda: [boys.boys_eval(xg, m, p, out=o) for (xg, m, p), o in zip(gx, go)]
+    grp_wall, grp_gpu = timed(torch, grouped, steps, 3)
+    del gx, go
     res = {"workload": "8,192 arrays, lengths logU[32,65536], n_max U{0..16}, "
                        "binary64/binary32 alternating, one graph-captured batched launch",
            "arguments": total, "ms": round(ms, 4), "values_per_s": values / (gpu / steps),
            "hbm_GBs": bytes_ / (ms * 1e-3) / 1e9, "tuning": best,
            "solo_calls_ms": round(solo_gpu / 2 * 1e3, 3),
            "batching_gain": round(solo_gpu / 2 / (gpu / steps), 2),
+           "grouped_plain_ms": round(grp_gpu / steps * 1e3, 4),
+           "grouped_plain_launches": len(groups),
            "tuning_cached": info["cached"],
            "candidates_ms": {k: round(v, 4) for k, v in info["times_ms"].items()}}
     plan.close()
