@@ -158,7 +158,11 @@ typedef struct {
  *             tile must be block x 1, 2 or 4.
  * schedule 2: one wave per tile (tile = 256, i.e. 64 lanes x 4 arguments; a block of
  *             64, 128 or 256 holds block / 64 tiles), so one workgroup can serve several
- *             short arrays.
+ *             short arrays.  With split_nmax > 0 the store-bound arrays, those with
+ *             n_max >= split_nmax (binary64 outputs) or n_max >= split_nmax + 4 (binary32
+ *             outputs), run first in a launch of their own with one workgroup of 256
+ *             threads per 256-argument tile (one argument per lane); the plan's graph holds
+ *             both launches.
  */
 typedef struct {
     int32_t tile;        /* arguments per tile, a multiple of the block size */
@@ -168,6 +172,8 @@ typedef struct {
     int32_t order;       /* tile order: 0 longest first; 1 array by array (each array's
                             tiles consecutive); 2 grouped by (precision, n_max), then
                             array by array */
+    int32_t split_nmax;  /* schedule 2: 0 (one launch) or 1..64 (above); must be 0 for
+                            schedules 0 and 1 */
 } boys_tuning;
 
 /*

@@ -249,7 +249,7 @@ def _tuning(t):
         return t
     return BoysTuning(int(t.get("tile", 0)), int(t.get("block", 0)),
                       int(t.get("grid_per_cu", 0)), int(t.get("schedule", 1)),
-                      int(t.get("order", 1)))
+                      int(t.get("order", 1)), int(t.get("split_nmax", 0)))
 
 
 class Plan:
@@ -308,8 +308,13 @@ def autotune(xs, n_maxs, precisions, candidates, warmup=2, reps=5, stream=None):
         st = _lib.lib().boys_autotune(arr, len(xs), cand, len(candidates), warmup, reps,
                                       _stream_ptr(stream, dev), ctypes.byref(best), times)
     _lib.check(st, "boys_autotune")
-    return ({"tile": best.tile, "block": best.block, "grid_per_cu": best.grid_per_cu,
-             "schedule": best.schedule, "order": best.order}, list(times))
+    # the caller's own candidate (as given) that the library picked
+    fields = [f for f, _ in BoysTuning._fields_]
+    key = [getattr(best, f) for f in fields]
+    for c, t in zip(candidates, cand):
+        if [getattr(t, f) for f in fields] == key:
+            return c, list(times)
+    return dict(zip(fields, key)), list(times)
 
 
 def max_nmax(precision="fp64") -> int:

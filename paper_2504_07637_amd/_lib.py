@@ -58,7 +58,7 @@ class BoysArray(ctypes.Structure):
 class BoysTuning(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("grid_per_cu", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("order", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("split_nmax", ctypes.c_int32)]
 
 
 class BoysServerConfig(ctypes.Structure):

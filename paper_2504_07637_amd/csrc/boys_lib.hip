@@ -182,9 +182,11 @@ struct boys_plan {
     int2 *d_tiles = nullptr;
     uint32_t *d_counter = nullptr;
     int32_t ntiles = 0;
+    int32_t ntiles_hi = 0;  // split_nmax > 0: the first ntiles_hi tiles form their own launch
     boys_tuning tuning{};
     int grid = 0;
-    int maxn = 0;
+    int maxn = 0;     // largest n_max of the (other) tiles
+    int maxn_hi = 0;  // largest n_max of the first ntiles_hi tiles
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -199,7 +201,8 @@ constexpr int kDefaultOrder = 1;
 
 boys_tuning resolve(const boys_tuning *t)
 {
-    boys_tuning r{kDefaultTile, kDefaultBlock, kDefaultGridPerCU, kDefaultSchedule, kDefaultOrder};
+    boys_tuning r{kDefaultTile, kDefaultBlock, kDefaultGridPerCU, kDefaultSchedule, kDefaultOrder,
+                  0};
     if (t) {
         if (t->tile > 0)
             r.tile = t->tile;
@@ -209,6 +212,7 @@ boys_tuning resolve(const boys_tuning *t)
             r.grid_per_cu = t->grid_per_cu;
         r.schedule = t->schedule;
         r.order = t->order;
+        r.split_nmax = t->split_nmax;
     }
     return r;
 }
@@ -219,6 +223,8 @@ bool tuning_ok(const boys_tuning &t)
     if (!block_ok || t.tile <= 0 || t.tile > (1 << 24))
         return false;
     if (t.order < 0 || t.order > 2)
+        return false;
+    if (t.split_nmax < 0 || t.split_nmax > 64 || (t.split_nmax != 0 && t.schedule != 2))
         return false;
     if (t.schedule == 0)
         return t.tile % t.block == 0 && t.grid_per_cu >= 1 && t.grid_per_cu <= 64;
@@ -264,21 +270,29 @@ boys_status build_schedule(boys_plan *p, const boys_array *arrays, int32_t count
         double cost;
         int32_t array;
         int32_t slice;
+        bool hi;  // in the one-argument-per-lane launch (split_nmax > 0)
     };
     std::vector<T> all;
-    int maxn = 0;
+    int maxn = 0, maxn_hi = 0;
+    const int split = p->tuning.split_nmax;
     for (int32_t a = 0; a < count; ++a) {
         const boys_array &A = arrays[a];
         p->host_desc[a] = Desc{A.x, A.out, A.n, A.ld_out, A.n_max, A.precision};
         const int64_t nt = (A.n + p->tuning.tile - 1) / p->tuning.tile;
         if (nt > INT32_MAX || (int64_t)all.size() + nt > INT32_MAX)
             return BOYS_ERR_INVALID_ARGUMENT;
+        const bool hi =
+            split > 0 && A.n_max >= split + (elem_bytes(A.precision) == 4 ? 4 : 0);
         for (int64_t t = 0; t < nt; ++t) {
             const int64_t cnt = std::min<int64_t>(p->tuning.tile, A.n - t * p->tuning.tile);
-            all.push_back({tile_cost(A, cnt), a, (int32_t)t});
+            all.push_back({tile_cost(A, cnt), a, (int32_t)t, hi});
         }
-        if (A.n > 0)
-            maxn = std::max(maxn, A.n_max);
+        if (A.n > 0) {
+            if (hi)
+                maxn_hi = std::max(maxn_hi, A.n_max);
+            else
+                maxn = std::max(maxn, A.n_max);
+        }
     }
     if (p->tuning.order == 0) {
         // longest processing time first (ties keep array order)
@@ -297,7 +311,11 @@ boys_status build_schedule(boys_plan *p, const boys_array *arrays, int32_t count
         });
     }
     // order 1: as built, array by array with each array's tiles consecutive, so the
-    // workgroups running at one time write neighbouring pieces of the same output rows
+    // workgroups running at one time write neighbouring pieces of the same output rows.
+    // The tiles of the store-bound arrays go first, in the same order, for their own launch.
+    const auto mid = std::stable_partition(all.begin(), all.end(), [](const T &t) { return t.hi; });
+    p->ntiles_hi = (int32_t)(mid - all.begin());
+    p->maxn_hi = maxn_hi;
     tiles.resize(all.size());
     for (size_t i = 0; i < all.size(); ++i)
         tiles[i] = make_int2(all[i].array, all[i].slice);
@@ -318,7 +336,16 @@ boys_status capture_graph(boys_plan *p)
         (void)hipStreamDestroy(s);
         return BOYS_ERR_DEVICE;
     }
-    if (boys_internal::launch_batched(p->d_desc, p->d_tiles, p->ntiles, p->d_counter, p->maxn,
+    // split plans: the store-bound arrays first, one workgroup of 256 threads per tile of
+    // 256 arguments (the plan's tile size), then the rest per wave
+    if (p->ntiles_hi > 0 &&
+        boys_internal::launch_batched(p->d_desc, p->d_tiles, p->ntiles_hi, p->d_counter,
+                                      p->maxn_hi, boys_internal::Launch{1, p->tuning.tile, 256, p->grid},
+                                      s) != hipSuccess)
+        st = BOYS_ERR_DEVICE;
+    if (st == BOYS_OK && p->ntiles > p->ntiles_hi &&
+        boys_internal::launch_batched(p->d_desc, p->d_tiles + p->ntiles_hi,
+                                      p->ntiles - p->ntiles_hi, p->d_counter, p->maxn,
                                       launch_of(p), s) != hipSuccess)
         st = BOYS_ERR_DEVICE;
     if (hipStreamEndCapture(s, &p->graph) != hipSuccess)

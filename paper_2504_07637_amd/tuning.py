@@ -8,7 +8,8 @@ device, library build and a coarse signature of the batch, and keeps it in a JSO
 Tunable choices (the per-argument work is one sequential chain, so a lane always owns
 whole arguments): the schedule (persistent workgroups with a work counter, one workgroup
 per tile, or one wave per tile), the workgroup size, the arguments per lane (tile =
-block x 1, 2 or 4 for one workgroup per tile, 64 x 4 for one wave per tile), the
+block x 1, 2 or 4 for one workgroup per tile, 64 x 4 for one wave per tile, with the
+store-bound arrays optionally in a launch of their own at one argument per lane), the
 tile order (longest first, array by array, or grouped by class) and, for the persistent
 schedule, the tile size and the number of workgroups per compute unit.
 """
@@ -28,6 +29,8 @@ CANDIDATES = (
        for o in (1, 0) for t in (1024, 4096) for g in (2, 4)]
     + [{"schedule": 2, "block": b, "tile": 256, "grid_per_cu": 1, "order": o}
        for o in (1, 2) for b in (128, 256)]
+    + [{"schedule": 2, "block": 256, "tile": 256, "grid_per_cu": 1, "order": 1, "split_nmax": k}
+       for k in (8, 10, 12)]
 )
 
 

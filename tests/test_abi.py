@@ -92,6 +92,10 @@ def test_argument_errors_are_reported_before_any_launch():
         assert lib.boys_plan_create(ctypes.byref(p), arr, 1, ctypes.byref(bad_wave)) == L.ERR_INVALID_ARGUMENT
     assert lib.boys_plan_create(ctypes.byref(p), arr, 1, ctypes.byref(L.BoysTuning(256, 256, 1, 3, 1))) \
         == L.ERR_INVALID_ARGUMENT  # no schedule 3
+    for bad_split in (L.BoysTuning(256, 256, 1, 1, 1, 8), L.BoysTuning(256, 256, 1, 2, 1, 65),
+                      L.BoysTuning(256, 256, 1, 2, 1, -1)):
+        # split plans: schedule 2 only, orders 1..64
+        assert lib.boys_plan_create(ctypes.byref(p), arr, 1, ctypes.byref(bad_split)) == L.ERR_INVALID_ARGUMENT
     assert lib.boys_plan_execute(None, None) == L.ERR_INVALID_ARGUMENT
     lib.boys_plan_destroy(None)
 

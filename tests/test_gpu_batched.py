@@ -109,7 +109,10 @@ def test_full_batched_workload_equals_solo():
     {"schedule": 1, "tile": 256, "block": 64, "grid_per_cu": 1, "order": 1},
     {"schedule": 2, "tile": 256, "block": 256, "grid_per_cu": 1, "order": 1},
     {"schedule": 2, "tile": 256, "block": 64, "grid_per_cu": 1, "order": 0},
-    {"schedule": 2, "tile": 256, "block": 128, "grid_per_cu": 1, "order": 2}])
+    {"schedule": 2, "tile": 256, "block": 128, "grid_per_cu": 1, "order": 2},
+    {"schedule": 2, "tile": 256, "block": 256, "grid_per_cu": 1, "order": 1, "split_nmax": 8},
+    {"schedule": 2, "tile": 256, "block": 64, "grid_per_cu": 1, "order": 0, "split_nmax": 1},
+    {"schedule": 2, "tile": 256, "block": 128, "grid_per_cu": 1, "order": 2, "split_nmax": 40}])
 def test_every_schedule_equals_solo(tuning):
     torch = require_gpu()
     import paper_2504_07637_amd as boys
