@@ -187,9 +187,11 @@ boys_status boys_eval_batched(const boys_array *arrays, int32_t count, void *str
 /*
  * Plans: a schedule (tiles in the tuning's order, descriptor and tile tables in
  * device memory, a work counter) and a HIP graph of the batched launch (schedule 0:
- * [reset counter, persistent kernel]; schedule 1: [one workgroup per tile]) built once
- * for a batch and replayed by boys_plan_execute.  tuning may be NULL for the
- * defaults.  boys_plan_update replaces the x/out pointers of a batch with the same
+ * [reset counter, persistent kernel]; schedule 1: [one workgroup per tile]; schedule 2:
+ * [one wave per tile], after [one workgroup per tile] for the store-bound arrays of a
+ * split plan) built once for a batch and replayed by boys_plan_execute.  tuning may be
+ * NULL for the defaults: schedule 2, tile 256, block 256, order 1, split_nmax 12.
+ * boys_eval_batched uses the defaults.  boys_plan_update replaces the x/out pointers of a batch with the same
  * count, lengths, n_max and precisions (other changes return BOYS_ERR_INVALID_ARGUMENT).
  * A plan belongs to the device that was current at creation.
  */

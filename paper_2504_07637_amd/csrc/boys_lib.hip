@@ -196,13 +196,17 @@ namespace {
 constexpr int kDefaultTile = 256;
 constexpr int kDefaultBlock = 256;
 constexpr int kDefaultGridPerCU = 4;
-constexpr int kDefaultSchedule = 1;
+// with no tuning: one wave per tile, the store-bound arrays (n_max >= 12, binary32 outputs
+// >= 16) in a launch of their own, the measured best for mixed batches; a batch of low
+// orders only, or of high orders only, gets a single launch
+constexpr int kDefaultSchedule = 2;
 constexpr int kDefaultOrder = 1;
+constexpr int kDefaultSplit = 12;
 
 boys_tuning resolve(const boys_tuning *t)
 {
     boys_tuning r{kDefaultTile, kDefaultBlock, kDefaultGridPerCU, kDefaultSchedule, kDefaultOrder,
-                  0};
+                  kDefaultSplit};
     if (t) {
         if (t->tile > 0)
             r.tile = t->tile;
