@@ -253,7 +253,11 @@ def _tuning(t):
 
 
 class Plan:
-    """A batched schedule captured in a HIP graph; execute() replays it."""
+    """A batched schedule captured in a HIP graph; execute() replays it.
+
+    tuning: None for the library defaults (one wave per tile, with the store-bound arrays
+    in a launch of their own), or a dict of boys_tuning fields (tile, block, grid_per_cu,
+    schedule, order, split_nmax)."""
 
     def __init__(self, xs, n_maxs, precisions, outs=None, tuning=None):
         torch = _torch()
@@ -295,9 +299,9 @@ class Plan:
 
 
 def autotune(xs, n_maxs, precisions, candidates, warmup=2, reps=5, stream=None):
-    """Time each candidate tuning (dicts with tile/block/grid_per_cu/schedule) on this batch.
+    """Time each candidate tuning (dicts of boys_tuning fields) on this batch.
 
-    Returns (best_tuning_dict, [ms per candidate])."""
+    Returns (the fastest candidate, as given, [ms per candidate])."""
     torch = _torch()
     arr, outs = _arrays(xs, n_maxs, precisions, None)
     cand = (BoysTuning * len(candidates))(*[_tuning(c) for c in candidates])
