@@ -143,9 +143,12 @@ def boys_eval(x, n_max: int, precision="fp64", out=None, stream=None):
         if out.shape[0] != n_max + 1 or out.shape[1] != n or out.stride(1) != 1:
             raise ValueError("out must be (n_max+1, n) with unit column stride")
     ld = out.stride(0) if n > 0 else max(n, 1)
-    with _on_device(dev):
-        st = _lib.lib().boys_eval(x.data_ptr(), n, n_max, out.data_ptr(), ld, code,
-                                  _stream_ptr(stream, dev))
+    fn = _lib.lib().boys_eval
+    if _single_device():  # nothing to switch: skip the guard (this call is latency-bound)
+        st = fn(x.data_ptr(), n, n_max, out.data_ptr(), ld, code, _stream_ptr(stream, dev))
+    else:
+        with _on_device(dev):
+            st = fn(x.data_ptr(), n, n_max, out.data_ptr(), ld, code, _stream_ptr(stream, dev))
     if st:
         _lib.check(st, "boys_eval")
     return out
@@ -272,10 +275,14 @@ class Plan:
         _lib.check(st, "boys_plan_create")
 
     def execute(self, stream=None):
-        torch = _torch()
-        with _on_device(self.device):
-            st = _lib.lib().boys_plan_execute(self._p, _stream_ptr(stream, self.device))
-        _lib.check(st, "boys_plan_execute")
+        fn = _lib.lib().boys_plan_execute
+        if _single_device():
+            st = fn(self._p, _stream_ptr(stream, self.device))
+        else:
+            with _on_device(self.device):
+                st = fn(self._p, _stream_ptr(stream, self.device))
+        if st:
+            _lib.check(st, "boys_plan_execute")
         return self.outs
 
     def update(self, xs, outs):
