@@ -283,6 +283,32 @@ def test_full_size_integral_workload_sampled():
         torch.cuda.empty_cache()
 
 
+def test_full_size_properties_of_every_output():
+    # every output of the 2^26-argument n_max = 16 workload, on the device, against what
+    # the function itself fixes at any size: 0 <= F_m <= 1/(2m+1) (F_m(0) = 1/(2m+1) and F_m
+    # decreases in x; up to the class's approximation error, 2^-40 in binary64 and 2^-12
+    # in the mixed class, whose F_16 carries about 15 bits), F_{m+1} <= F_m (t^(2m+2) <=
+    # t^(2m) on [0, 1]; the ratio is at most (2m+1)/(2m+3), far from 1), and, in binary64,
+    # the recursion identity (2m+1) F_m = 2x F_{m+1} + exp(-x) to a relative 2^-40
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    n_args, n = 1 << 26, 16
+    xd = torch.from_numpy(inputs.integral_args(n_args, seed=2)).to("cuda")
+    m = torch.arange(n + 1, device="cuda", dtype=torch.float64).unsqueeze(1)
+    for prec, tol in (("fp64", 2.0 ** -40), ("fp32", 2.0 ** -12)):
+        _say(f"[properties] {prec} n_max={n} count={n_args}")
+        F = boys.boys_eval(xd, n, prec).double()
+        assert bool(torch.all(F >= 0)), prec
+        assert bool(torch.all(F <= (1.0 / (2 * m + 1)) * (1 + tol))), prec
+        assert bool(torch.all(F[1:] <= F[:-1])), prec
+        if prec == "fp64":
+            lhs = (2 * m[:-1] + 1) * F[:-1]
+            rhs = 2 * xd * F[1:] + torch.exp(-xd)
+            assert bool(torch.all((lhs - rhs).abs() <= 2.0 ** -40 * lhs)), prec
+        del F
+        torch.cuda.empty_cache()
+
+
 def test_runs_on_a_side_stream():
     torch = require_gpu()
     import paper_2504_07637_amd as boys
