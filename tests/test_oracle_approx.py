@@ -194,3 +194,76 @@ def test_pin_detects_planted_mistakes():
     swap.fields["ug"], swap.fields["vg"] = r["vg"], r["ug"]
     got = ebar("fp64", 16, swap, k=1 << 12)
     assert got["ebn"] < 20
+
+
+def _w_binary32(x, r, n):
+    """W = Q~^n sqrt(Q~) e of the mixed class, recomputed here in numpy binary32 from the
+    record's binary32 coefficients (Eqs. pqz, pz, qz, fq; left to right as written), with
+    e = RN32(RN64(exp(-x))) taken from mpmath at 50 digits."""
+    mpmath = pytest.importorskip("mpmath")
+    f32 = np.float32
+    xf = x.astype(f32)
+    with mpmath.workdps(50):
+        e = np.array([float(mpmath.exp(-mpmath.mpf(float(v)))) for v in x]).astype(f32)
+
+    def fac(g, q, l):
+        p = np.ones_like(xf)
+        for gk in reversed(g):
+            p = p * xf + f32(gk)
+        for k in range(len(q) // 2):
+            d = xf - f32(q[2 * k])
+            p = p * (d * d + f32(q[2 * k + 1]))
+        for lk in l:
+            p = p * (xf - f32(lk))
+        return p
+
+    u = fac(r["ug"], r["uq"], r["ul"])
+    v = fac(r["vg"], r["vq"], r["vl"])
+    Q = (f32(r["q0"]) + f32(r["q1"]) * xf) + ((f32(r["q2"]) * (u / v)) * xf) * xf
+    P = np.ones_like(Q) if n == 0 else Q.copy()
+    if n > 0:
+        for b in range(int(n).bit_length() - 2, -1, -1):
+            P = P * P
+            if (n >> b) & 1:
+                P = P * Q
+    return (P * np.sqrt(Q)) * e
+
+
+@pytest.mark.parametrize("n", [0, 1, 4, 8, 16, 20, 27, 36])
+def test_mixed_class_binary64_stage(n):
+    # The mixed class takes G = x + W and c_n / G^(n+1/2) (Eq. fq) in binary64, on the
+    # binary64 argument: with W as binary32 arithmetic leaves it, F_n must be the exact
+    # c_n / (x + W)^(n+1/2) rounded to binary32, within one binary32 ulp.  In binary32
+    # (G = RN32(x) + W, or (kappa_n / G)^(n+1/2)) the power amplifies a rounding of G by
+    # n + 1/2: several ulps from n = 4 on, which this catches.
+    mpmath = pytest.importorskip("mpmath")
+    r = orc.record("fp32", n)
+    g = np.random.default_rng(1000 + n)
+    x = np.concatenate([np.sort(g.uniform(0.0, r["z"], 1500)),
+                        np.exp(g.uniform(np.log(1e-6), np.log(1.0), 300))])
+    W = _w_binary32(x, r, n)
+    got = orc.approx_mixed(x, n)[n]
+    s = mpmath.mpf(n) + mpmath.mpf(1) / 2
+    with mpmath.workdps(50):
+        c = mpmath.gamma(s) / 2
+        want = np.array([float(c / (mpmath.mpf(float(xi)) + mpmath.mpf(float(wi))) ** s)
+                         for xi, wi in zip(x, W)]).astype(np.float32)
+    d = np.abs(got.view(np.int32).astype(np.int64) - want.view(np.int32).astype(np.int64))
+    assert d.max() <= 1, (n, x[np.argmax(d)], int(d.max()))
+
+
+@pytest.mark.parametrize("n", [8, 12, 16, 24, 36])
+def test_mixed_class_beats_all_binary32_in_the_recursion(n):
+    # The binary64 power is what sets the mixed class apart from Table 1's all-binary32
+    # arithmetic: on Table 1's grid its F_m gain at least half a bit at some mid order.
+    r = orc.record("fp32", n)
+    x = np.arange(1 << 14) * (r["z"] / (1 << 14))
+    A = orc.approx_mixed(x, n).astype(np.float64)
+    S = orc.approx_single(x, n).astype(np.float64)
+    gains = []
+    for m in range(n // 4, 3 * n // 4 + 1):
+        hi, lo = orc.exact_one(x, m)
+        ok = np.abs(hi) >= 1.1754943508222875e-38
+        gains.append(orc.bits(orc.rel_err(A[m][ok], hi[ok], lo[ok]))
+                     - orc.bits(orc.rel_err(S[m][ok], hi[ok], lo[ok])))
+    assert max(gains) >= 0.5, (n, gains)
