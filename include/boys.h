@@ -89,6 +89,19 @@ boys_status boys_eval(const double *x, int64_t n, int32_t n_max, void *out, int6
                       int32_t precision, void *stream);
 
 /*
+ * The evaluation of boys_eval, storing only some of the orders: bit m of rows (m = 0..n_max)
+ * selects F_m, and the k-th selected order, counting upward from m = 0, is written to
+ * out[k * ld_out + i] (k = 0..popcount(rows)-1; row layout and element type as boys_eval).
+ * Every order is still computed in full (the recursion of Eq. r and the upward product of
+ * Eq. limf1 pass through all of them), so each stored value equals, bit for bit, the one
+ * boys_eval stores for that order.  For consumers that need a few orders, and to measure the
+ * arithmetic without the full (n_max+1)-row store.  BOYS_ERR_INVALID_ARGUMENT when rows is 0
+ * or selects an order above n_max; other errors as boys_eval (with ld_out >= n).
+ */
+boys_status boys_eval_rows(const double *x, int64_t n, int32_t n_max, uint64_t rows, void *out,
+                           int64_t ld_out, int32_t precision, void *stream);
+
+/*
  * The two-approximation option of section "Computations", binary64: when the highest
  * accuracy is wanted for the orders m = 0..n_bar, F_{n_bar} and F_{n_max} are both taken
  * from their own best approximants (cut-offs z_{n_bar,53} and z_{n_max,53}) and two
@@ -191,9 +204,13 @@ boys_status boys_eval_batched(const boys_array *arrays, int32_t count, void *str
  * [one wave per tile], after [one workgroup per tile] for the store-bound arrays of a
  * split plan) built once for a batch and replayed by boys_plan_execute.  tuning may be
  * NULL for the defaults: schedule 2, tile 256, block 256, order 1, split_nmax 12.
- * boys_eval_batched uses the defaults.  boys_plan_update replaces the x/out pointers of a batch with the same
- * count, lengths, n_max and precisions (other changes return BOYS_ERR_INVALID_ARGUMENT).
- * A plan belongs to the device that was current at creation.
+ * boys_eval_batched uses the defaults.  boys_plan_update replaces the x/out pointers of a
+ * batch with the same count, lengths, n_max and precisions (other changes return
+ * BOYS_ERR_INVALID_ARGUMENT); it first waits for every execute of the plan already
+ * enqueued (on any stream) to finish, so executes enqueued before it use the old pointers
+ * and executes enqueued after it returns use the new ones.  boys_plan_destroy also waits
+ * for the plan's enqueued executes.  A plan belongs to the device that was current at
+ * creation.
  */
 typedef struct boys_plan boys_plan;
 boys_status boys_plan_create(boys_plan **plan, const boys_array *arrays, int32_t count,
@@ -226,7 +243,13 @@ boys_status boys_autotune(const boys_array *arrays, int32_t count, const boys_tu
  *     (continuous batching);
  *   - a request completes when its batch's event completes; its output stays in device
  *     memory until boys_server_release (rows of ld elements, ld = n rounded up to a
- *     multiple of 16 binary64 / 32 binary32 elements).
+ *     multiple of 16 binary64 / 32 binary32 elements);
+ *   - a request fails, instead, when its batch could not be launched (the server then
+ *     waits for whatever part of the batch it had enqueued) or its completion event
+ *     reports a device error.  Failed requests are reported by boys_server_poll like
+ *     completed ones; boys_server_result and boys_server_copy_result return
+ *     BOYS_ERR_DEVICE for them, and they are released like completed ones.  A failed
+ *     batch is not retried.
  * Times are seconds on the server's monotonic clock.  x_host must stay valid and
  * unchanged until the request completes.  All functions are thread-safe.
  */
@@ -244,6 +267,7 @@ typedef struct {
     uint64_t queued_now, inflight_now, max_queued, max_inflight;
     uint64_t bytes_in_use, max_bytes_in_use;
     uint64_t device_errors;
+    uint64_t failed;      /* requests that failed (also counted in completed) */
 } boys_server_stats;
 /* cfg is a host struct; the server is bound to the device current at creation. */
 boys_status boys_server_create(boys_server **server, const boys_server_config *cfg);
@@ -255,14 +279,21 @@ boys_status boys_server_submit(boys_server *server, const double *x_host, int64_
 /* Writes up to max ids of requests completed since the last poll; returns their count. */
 int32_t boys_server_poll(boys_server *server, uint64_t *ids, int32_t max);
 /* For a completed, unreleased request: device pointer of its output rows, their leading
-   dimension, and its submit and completion times. */
+   dimension, and its submit and completion times (BOYS_ERR_DEVICE for a failed request).
+   A client that reads the rows through this pointer with work of its own must have
+   finished those reads (for example, synchronised their stream) before it releases the
+   request; reads through boys_server_copy_result are tracked by the server. */
 boys_status boys_server_result(boys_server *server, uint64_t id, const void **out,
                                int64_t *ld, double *t_submit, double *t_done);
 /* Copies a completed, unreleased request's (n_max+1) output rows into the device buffer
-   dst (row stride ld_dst >= n elements of the request's precision), enqueued on stream. */
+   dst (row stride ld_dst >= n elements of the request's precision), enqueued on stream
+   (BOYS_ERR_DEVICE for a failed request).  The request may be released right after the
+   call: the server records an event on stream behind the copy and keeps the request's
+   memory until that event has completed. */
 boys_status boys_server_copy_result(boys_server *server, uint64_t id, void *dst, int64_t ld_dst,
                                     void *stream);
-/* Frees a completed request's device memory (its output pointer becomes invalid). */
+/* Releases a completed or failed request: its output pointer becomes invalid, and its
+   device memory is freed once the copies enqueued by boys_server_copy_result are done. */
 boys_status boys_server_release(boys_server *server, uint64_t id);
 boys_status boys_server_get_stats(boys_server *server, boys_server_stats *stats);
 /* Waits until no admitted request is waiting for a slot or running and the queue is

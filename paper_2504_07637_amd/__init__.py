@@ -17,7 +17,7 @@ import ctypes
 from . import _lib
 from ._lib import FP32, FP32S, FP32X, FP64, FP64_PLUS, BoysArray, BoysError, BoysTuning
 
-__all__ = ["boys_eval", "boys_eval_split", "boys_eri_ssss", "boys_eval_batched", "Plan", "autotune", "max_nmax", "cutoff",
+__all__ = ["boys_eval", "boys_eval_rows", "boys_eval_split", "boys_eri_ssss", "boys_eval_batched", "Plan", "autotune", "max_nmax", "cutoff",
            "precision_code", "padded_ld", "empty_out", "BoysError", "FP64", "FP32", "FP64_PLUS",
            "FP32X", "FP32S"]
 
@@ -151,6 +151,32 @@ def boys_eval(x, n_max: int, precision="fp64", out=None, stream=None):
             st = fn(x.data_ptr(), n, n_max, out.data_ptr(), ld, code, _stream_ptr(stream, dev))
     if st:
         _lib.check(st, "boys_eval")
+    return out
+
+
+def boys_eval_rows(x, n_max: int, rows, precision="fp64", out=None, stream=None):
+    """The orders listed in `rows` (each 0..n_max) of the order-n_max evaluation, as a
+    (len(rows), len(x)) tensor in increasing order of m; every order is still computed
+    (each stored row equals that row of boys_eval bit for bit)."""
+    _check_x(x)
+    code = precision_code(precision)
+    sel = sorted(set(int(m) for m in rows))
+    if not sel or sel[0] < 0 or sel[-1] > n_max:
+        raise ValueError("rows must name orders 0..n_max")
+    mask = 0
+    for m in sel:
+        mask |= 1 << m
+    n = x.numel()
+    if out is None:
+        out = empty_out(n, len(sel) - 1, code, x.device)
+    elif (out.dtype != _out_dtype(code) or out.device != x.device or out.dim() != 2
+          or out.shape[0] != len(sel) or out.shape[1] != n or out.stride(1) != 1):
+        raise ValueError("out must be (len(rows), n) of the class's dtype, unit column stride")
+    ld = out.stride(0) if n > 0 else 1
+    with _on_device(x.device):
+        st = _lib.lib().boys_eval_rows(x.data_ptr(), n, n_max, mask, out.data_ptr(), ld, code,
+                                       _stream_ptr(stream, x.device))
+    _lib.check(st, "boys_eval_rows")
     return out
 
 

@@ -26,6 +26,7 @@ ERR_DEVICE = 4
 # every function declared in include/boys.h
 EXPORTS = (
     "boys_eval",
+    "boys_eval_rows",
     "boys_eval_split",
     "boys_eri_ssss",
     "boys_eval_batched",
@@ -77,7 +78,7 @@ class BoysServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in (
         "submitted", "admitted", "launched", "completed", "released", "batches",
         "queued_now", "inflight_now", "max_queued", "max_inflight",
-        "bytes_in_use", "max_bytes_in_use", "device_errors")]
+        "bytes_in_use", "max_bytes_in_use", "device_errors", "failed")]
 
 
 class BoysError(RuntimeError):
@@ -100,6 +101,8 @@ def lib():
         vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
         L.boys_eval.argtypes = [vp, i64, i32, vp, i64, i32, vp]
         L.boys_eval.restype = ctypes.c_int
+        L.boys_eval_rows.argtypes = [vp, i64, i32, ctypes.c_uint64, vp, i64, i32, vp]
+        L.boys_eval_rows.restype = ctypes.c_int
         L.boys_eval_split.argtypes = [vp, i64, i32, i32, vp, i64, vp]
         L.boys_eval_split.restype = ctypes.c_int
         L.boys_eri_ssss.argtypes = [ctypes.POINTER(BoysPairList), ctypes.POINTER(BoysPairList),

@@ -39,11 +39,12 @@ hipError_t launch_batched(const Desc *d_desc, const int2 *d_tiles, int32_t ntile
 int cu_count();
 
 // the plain launch of precision class C at order n (nullptr outside 0..the class's largest
-// order); defined per class in plain_inst.hip
+// order); with select_rows, the form that stores only the rows whose bit is set in `rows`
+// (boys_eval_rows), otherwise `rows` is ignored; defined per class in plain_inst.hip
 using PlainLaunch = hipError_t (*)(const double *x, int64_t n, void *out, int64_t ld,
-                                   hipStream_t s);
+                                   uint64_t rows, hipStream_t s);
 template <int C>
-PlainLaunch plain_launcher(int n);
+PlainLaunch plain_launcher(int n, bool select_rows);
 
 // the two-approximation launch at order n (1..the binary64 maximum; nullptr otherwise);
 // defined in split_inst.hip

@@ -6,9 +6,10 @@
 // unit holds only the kernels it instantiates.
 //
 // Kernels (gfx950, wave64):
-//   k_plain<C, N>    one lane per argument, one argument per lane (a full grid: for the
+//   k_plain<C, N, Sel>  one lane per argument, one argument per lane (a full grid: for the
 //                    (n_max+1)-row output this launch shape keeps the HBM write streams
-//                    densest); x is read and the output rows are written with coalesced
+//                    densest; Sel: only selected rows are stored, boys_eval_rows);
+//                    x is read and the output rows are written with coalesced
 //                    non-temporal accesses (for a wave, 512 contiguous bytes per binary64
 //                    row).  The binary64-output classes read the 4 KiB exp table through
 //                    the L1 cache with 128-thread workgroups; the binary32-output classes
@@ -92,6 +93,53 @@ __device__ __forceinline__ void store_rows_f32(const double *F, float *p, int64_
     }
 }
 
+// Row selection (boys_eval_rows): only the orders whose bit is set in `rows` (a kernel
+// argument, so every test is a scalar branch) are stored, the k-th selected one to row k.
+// Every F_m is still computed: the recursion and the upward chain pass through all orders.
+template <int N, typename T>
+__device__ __forceinline__ void store_rows_sel(const T *F, T *p, int64_t ld, uint64_t rows)
+{
+#pragma unroll
+    for (int m = 0; m <= N; ++m) {
+        if ((rows >> m) & 1u) {
+            store_nt(F[m], p);
+            p += ld;
+        }
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void store_rows_sel_f32(const double *F, float *p, int64_t ld,
+                                                   uint64_t rows)
+{
+#pragma unroll
+    for (int m = 0; m <= N; ++m) {
+        if ((rows >> m) & 1u) {
+            store_nt((float)F[m], p);
+            p += ld;
+        }
+    }
+}
+
+// every row (Sel = false) or the selected ones
+template <bool Sel, int N, typename T>
+__device__ __forceinline__ void store_out(const T *F, T *p, int64_t ld, uint64_t rows)
+{
+    if constexpr (Sel)
+        store_rows_sel<N>(F, p, ld, rows);
+    else
+        store_rows<N>(F, p, ld);
+}
+
+template <bool Sel, int N>
+__device__ __forceinline__ void store_out_f32(const double *F, float *p, int64_t ld, uint64_t rows)
+{
+    if constexpr (Sel)
+        store_rows_sel_f32<N>(F, p, ld, rows);
+    else
+        store_rows_f32<N>(F, p, ld);
+}
+
 __device__ __forceinline__ void load_exp_table(double2 *tab)
 {
     for (int t = threadIdx.x; t < 256; t += blockDim.x)
@@ -99,58 +147,62 @@ __device__ __forceinline__ void load_exp_table(double2 *tab)
     __syncthreads();
 }
 
-template <int N>
+template <int N, bool Sel = false>
 __device__ __forceinline__ void body_f64(const double *__restrict__ x, double *__restrict__ out,
-                                         int64_t ld, int64_t i, const double2 *tab)
+                                         int64_t ld, int64_t i, const double2 *tab,
+                                         uint64_t rows = 0)
 {
     double F[N + 1];
     boys::eval_f64<N>(load_nt(x + i), tab, F);
-    store_rows<N>(F, out + i, ld);
+    store_out<Sel, N>(F, out + i, ld, rows);
 }
 
 // binary64, F_0..F_N from the order N+1 approximant and one more recursion step
-template <int N>
+template <int N, bool Sel = false>
 __device__ __forceinline__ void body_f64plus(const double *__restrict__ x,
                                              double *__restrict__ out, int64_t ld, int64_t i,
-                                             const double2 *tab)
+                                             const double2 *tab, uint64_t rows = 0)
 {
     double F[N + 2];
     boys::eval_f64<N + 1>(load_nt(x + i), tab, F);
-    store_rows<N>(F, out + i, ld);
+    store_out<Sel, N>(F, out + i, ld, rows);
 }
 
 // binary32 output from binary64 arithmetic with the ~28-bit approximants; each value is
 // rounded once to binary32 at the store
-template <int N>
+template <int N, bool Sel = false>
 __device__ __forceinline__ void body_f32x(const double *__restrict__ x, float *__restrict__ out,
-                                          int64_t ld, int64_t i, const double2 *tab)
+                                          int64_t ld, int64_t i, const double2 *tab,
+                                          uint64_t rows = 0)
 {
     double F[N + 1];
     boys::eval_f32r<N>(load_nt(x + i), tab, F);
-    store_rows_f32<N>(F, out + i, ld);
+    store_out_f32<Sel, N>(F, out + i, ld, rows);
 }
 
 // one argument of class C (a boys_precision value) at order N
 template <int C, int N>
 __device__ __forceinline__ void body(const Desc &d, int64_t i, const double2 *tab);
 
-template <int N>
+template <int N, bool Sel = false>
 __device__ __forceinline__ void body_f32(const double *__restrict__ x, float *__restrict__ out,
-                                         int64_t ld, int64_t i, const double2 *tab)
+                                         int64_t ld, int64_t i, const double2 *tab,
+                                         uint64_t rows = 0)
 {
     float F[N + 1];
     boys::eval_f32<N>(load_nt(x + i), tab, F);
-    store_rows<N>(F, out + i, ld);
+    store_out<Sel, N>(F, out + i, ld, rows);
 }
 
 // all binary32 below the cut-off (Table 1's binary32 arithmetic)
-template <int N>
+template <int N, bool Sel = false>
 __device__ __forceinline__ void body_f32s(const double *__restrict__ x, float *__restrict__ out,
-                                          int64_t ld, int64_t i, const double2 *tab)
+                                          int64_t ld, int64_t i, const double2 *tab,
+                                          uint64_t rows = 0)
 {
     float F[N + 1];
     boys::eval_f32s<N>(load_nt(x + i), tab, F);
-    store_rows<N>(F, out + i, ld);
+    store_out<Sel, N>(F, out + i, ld, rows);
 }
 
 constexpr int cmin(int a, int b)
@@ -228,9 +280,11 @@ constexpr bool plain_lds_table()
         return false;
 }
 
-template <int C, int N>
+// Sel: store only the rows selected by `rows` (boys_eval_rows); otherwise `rows` is unused
+template <int C, int N, bool Sel>
 __global__ __launch_bounds__(plain_block<C>()) void k_plain(const double *__restrict__ x, int64_t n,
-                                                            void *__restrict__ out, int64_t ld)
+                                                            void *__restrict__ out, int64_t ld,
+                                                            uint64_t rows)
 {
     constexpr int BS = plain_block<C>();
     const double2 *tab;
@@ -246,15 +300,15 @@ __global__ __launch_bounds__(plain_block<C>()) void k_plain(const double *__rest
     const int64_t i = (int64_t)block_index<xcd_contiguous<C, N>()>() * BS + threadIdx.x;
     if (i < n) {
         if constexpr (C == BOYS_FP64)
-            body_f64<N>(x, static_cast<double *>(out), ld, i, tab);
+            body_f64<N, Sel>(x, static_cast<double *>(out), ld, i, tab, rows);
         else if constexpr (C == BOYS_FP64_PLUS)
-            body_f64plus<N>(x, static_cast<double *>(out), ld, i, tab);
+            body_f64plus<N, Sel>(x, static_cast<double *>(out), ld, i, tab, rows);
         else if constexpr (C == BOYS_FP32X)
-            body_f32x<N>(x, static_cast<float *>(out), ld, i, tab);
+            body_f32x<N, Sel>(x, static_cast<float *>(out), ld, i, tab, rows);
         else if constexpr (C == BOYS_FP32_SINGLE)
-            body_f32s<N>(x, static_cast<float *>(out), ld, i, tab);
+            body_f32s<N, Sel>(x, static_cast<float *>(out), ld, i, tab, rows);
         else
-            body_f32<N>(x, static_cast<float *>(out), ld, i, tab);
+            body_f32<N, Sel>(x, static_cast<float *>(out), ld, i, tab, rows);
     }
 }
 

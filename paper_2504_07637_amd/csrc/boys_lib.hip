@@ -56,19 +56,19 @@ int cu_count()
 
 using boys_internal::PlainLaunch;
 
-PlainLaunch plain_launcher(int32_t prec, int n)
+PlainLaunch plain_launcher(int32_t prec, int n, bool select_rows)
 {
     switch (prec) {
     case BOYS_FP64:
-        return boys_internal::plain_launcher<BOYS_FP64>(n);
+        return boys_internal::plain_launcher<BOYS_FP64>(n, select_rows);
     case BOYS_FP32:
-        return boys_internal::plain_launcher<BOYS_FP32>(n);
+        return boys_internal::plain_launcher<BOYS_FP32>(n, select_rows);
     case BOYS_FP64_PLUS:
-        return boys_internal::plain_launcher<BOYS_FP64_PLUS>(n);
+        return boys_internal::plain_launcher<BOYS_FP64_PLUS>(n, select_rows);
     case BOYS_FP32X:
-        return boys_internal::plain_launcher<BOYS_FP32X>(n);
+        return boys_internal::plain_launcher<BOYS_FP32X>(n, select_rows);
     case BOYS_FP32_SINGLE:
-        return boys_internal::plain_launcher<BOYS_FP32_SINGLE>(n);
+        return boys_internal::plain_launcher<BOYS_FP32_SINGLE>(n, select_rows);
     }
     return nullptr;
 }
@@ -189,6 +189,9 @@ struct boys_plan {
     int maxn_hi = 0;  // largest n_max of the first ntiles_hi tiles
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // one event per stream the plan was executed on, recorded behind each execute, so
+    // that update and destroy can wait for replays still reading the plan's tables
+    std::vector<std::pair<hipStream_t, hipEvent_t>> exec_events;
 };
 
 namespace {
@@ -246,8 +249,24 @@ double tile_cost(const boys_array &a, int64_t cnt)
     return bytes * (double)cnt;
 }
 
+// wait for every execute of the plan enqueued so far
+hipError_t wait_executes(boys_plan *p)
+{
+    hipError_t r = hipSuccess;
+    for (auto &se : p->exec_events) {
+        const hipError_t e = hipEventSynchronize(se.second);
+        if (e != hipSuccess && r == hipSuccess)
+            r = e;
+    }
+    return r;
+}
+
 void free_plan_buffers(boys_plan *p)
 {
+    (void)wait_executes(p);
+    for (auto &se : p->exec_events)
+        (void)hipEventDestroy(se.second);
+    p->exec_events.clear();
     if (p->exec)
         (void)hipGraphExecDestroy(p->exec);
     if (p->graph)
@@ -387,10 +406,31 @@ boys_status boys_eval(const double *x, int64_t n, int32_t n_max, void *out, int6
     if (st != BOYS_OK || n == 0)
         return st;
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    const PlainLaunch launch = plain_launcher(precision, n_max);
+    const PlainLaunch launch = plain_launcher(precision, n_max, false);
     if (launch == nullptr)
         return BOYS_ERR_UNSUPPORTED_NMAX;
-    return launch(x, n, out, ld_out, s) == hipSuccess ? BOYS_OK : BOYS_ERR_DEVICE;
+    return launch(x, n, out, ld_out, 0, s) == hipSuccess ? BOYS_OK : BOYS_ERR_DEVICE;
+}
+
+boys_status boys_eval_rows(const double *x, int64_t n, int32_t n_max, uint64_t rows, void *out,
+                           int64_t ld_out, int32_t precision, void *stream)
+{
+    // the selected rows are written as rows 0..k-1 of out: check the array as one of
+    // k - 1 orders
+    if (n_max < 0 || n_max > max_nmax(precision))
+        return max_nmax(precision) < 0 ? BOYS_ERR_INVALID_ARGUMENT : BOYS_ERR_UNSUPPORTED_NMAX;
+    if (rows == 0 || (n_max < 63 && (rows >> (n_max + 1)) != 0))
+        return BOYS_ERR_INVALID_ARGUMENT;
+    const int k = __builtin_popcountll(rows);
+    const boys_status st = check_array(x, n, k - 1, out, ld_out, precision);
+    if (st != BOYS_OK || n == 0)
+        return st;
+    const PlainLaunch launch = plain_launcher(precision, n_max, true);
+    if (launch == nullptr)
+        return BOYS_ERR_UNSUPPORTED_NMAX;
+    return launch(x, n, out, ld_out, rows, static_cast<hipStream_t>(stream)) == hipSuccess
+               ? BOYS_OK
+               : BOYS_ERR_DEVICE;
 }
 
 boys_status boys_eval_split(const double *x, int64_t n, int32_t n_bar, int32_t n_max, void *out,
@@ -502,6 +542,9 @@ boys_status boys_plan_update(boys_plan *p, const boys_array *arrays, int32_t cou
         if (o.n != A.n || o.n_max != A.n_max || o.precision != A.precision)
             return BOYS_ERR_INVALID_ARGUMENT;
     }
+    // replays enqueued before this call may still be reading the descriptors
+    if (wait_executes(p) != hipSuccess)
+        return BOYS_ERR_DEVICE;
     for (int32_t a = 0; a < count; ++a) {
         p->arrays[a] = arrays[a];
         p->host_desc[a].x = arrays[a].x;
@@ -520,9 +563,19 @@ boys_status boys_plan_execute(boys_plan *p, void *stream)
         return BOYS_ERR_INVALID_ARGUMENT;
     if (p->exec == nullptr)
         return BOYS_OK;  // empty batch
-    if (hipGraphLaunch(p->exec, static_cast<hipStream_t>(stream)) != hipSuccess)
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipGraphLaunch(p->exec, s) != hipSuccess)
         return BOYS_ERR_DEVICE;
-    return BOYS_OK;
+    hipEvent_t ev = nullptr;
+    for (auto &se : p->exec_events)
+        if (se.first == s)
+            ev = se.second;
+    if (ev == nullptr) {
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+            return BOYS_ERR_DEVICE;
+        p->exec_events.emplace_back(s, ev);
+    }
+    return hipEventRecord(ev, s) == hipSuccess ? BOYS_OK : BOYS_ERR_DEVICE;
 }
 
 void boys_plan_destroy(boys_plan *p)

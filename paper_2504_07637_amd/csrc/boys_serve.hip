@@ -7,9 +7,13 @@
 //   * K execution slots, each a HIP stream with its own pinned staging and device
 //     buffers for the descriptor and tile tables and its own work counter;
 //   * a launch on a slot enqueues, in stream order, the host-to-device copies of the
-//     batch's arguments and tables, then [zero counter, persistent batched kernel]
-//     (the same kernel and bodies as boys_eval), then an event; the slot is free again
+//     batch's arguments and tables, then the batched kernel with one workgroup per tile
+//     (the same per-argument bodies as boys_eval), then an event; the slot is free again
 //     when the event has completed, which is also the completion time of its requests.
+//     A launch that cannot be enqueued completely waits for what it did enqueue and
+//     fails its batch; an event that reports a device error fails its batch too;
+//   * boys_server_copy_result records an event on the client's stream after its copy;
+//     a released request keeps its memory until those events have completed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -47,22 +51,56 @@ struct HipExec {
     std::vector<Desc *> d_desc;
     std::vector<int2 *> d_tiles;
     std::vector<uint32_t *> d_counter;
+    std::vector<hipEvent_t> read_events;       // every read event created
+    std::vector<hipEvent_t> read_events_free;  // those not in use
     std::atomic<uint64_t> errors{0};
 
     int64_t tile_args() const { return tile; }
     int64_t max_tiles() const { return cap_tiles; }
 
-    bool done(int s)
+    boys_serve::SlotStatus status(int s)
     {
         const hipError_t e = hipEventQuery(events[s]);
         if (e == hipSuccess)
-            return true;
-        if (e != hipErrorNotReady) {
-            errors++;
-            return true;  // report the batch as finished; the error is counted
-        }
-        return false;
+            return boys_serve::SlotStatus::Done;
+        if (e == hipErrorNotReady)
+            return boys_serve::SlotStatus::Running;
+        errors++;
+        return boys_serve::SlotStatus::Failed;
     }
+
+    // an event recorded on the client's stream after a read of a result (nullptr if none
+    // could be recorded)
+    void *read_token(hipStream_t client)
+    {
+        hipEvent_t ev = nullptr;
+        if (!read_events_free.empty()) {
+            ev = read_events_free.back();
+            read_events_free.pop_back();
+        } else {
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+                return nullptr;
+            read_events.push_back(ev);
+        }
+        if (hipEventRecord(ev, client) != hipSuccess) {
+            read_events_free.push_back(ev);
+            return nullptr;
+        }
+        return ev;
+    }
+
+    // a read that reports a device error will never complete: its memory is given back
+    bool read_done(void *t)
+    {
+        const hipError_t e = hipEventQuery(static_cast<hipEvent_t>(t));
+        if (e == hipErrorNotReady)
+            return false;
+        if (e != hipSuccess)
+            errors++;
+        return true;
+    }
+
+    void read_free(void *t) { read_events_free.push_back(static_cast<hipEvent_t>(t)); }
 
     bool launch(int s, const std::vector<Request *> &batch)
     {
@@ -108,8 +146,13 @@ struct HipExec {
         ok = ok && boys_internal::launch_batched(d_desc[s], d_tiles[s], (int32_t)ts.size(),
                                                  d_counter[s], maxn, L, st) == hipSuccess;
         ok = ok && hipEventRecord(events[s], st) == hipSuccess;
-        if (!ok)
+        if (!ok) {
+            // wait for whatever part of the batch was enqueued (copies from the slot's
+            // staging and into the requests' memory), so that nothing of it is pending
+            (void)hipStreamSynchronize(st);
+            (void)hipGetLastError();
             errors++;
+        }
         return ok;
     }
 };
@@ -152,6 +195,13 @@ void scheduler(boys_server *s)
 
 void destroy_exec(HipExec &ex)
 {
+    // reads of results that clients enqueued and have not finished
+    for (hipEvent_t ev : ex.read_events) {
+        (void)hipEventSynchronize(ev);
+        (void)hipEventDestroy(ev);
+    }
+    ex.read_events.clear();
+    ex.read_events_free.clear();
     for (size_t i = 0; i < ex.streams.size(); ++i) {
         if (ex.streams[i]) {
             (void)hipStreamSynchronize(ex.streams[i]);
@@ -289,6 +339,8 @@ boys_status boys_server_result(boys_server *s, uint64_t id, const void **out, in
         return BOYS_ERR_INVALID_ARGUMENT;
     std::lock_guard<std::mutex> lk(s->mu);
     const Request *r = s->core->find(id);
+    if (r != nullptr && r->state == boys_serve::State::Failed)
+        return BOYS_ERR_DEVICE;
     if (r == nullptr || r->state != boys_serve::State::Done)
         return BOYS_ERR_INVALID_ARGUMENT;
     if (out)
@@ -312,6 +364,8 @@ boys_status boys_server_copy_result(boys_server *s, uint64_t id, void *dst, int6
     {
         std::lock_guard<std::mutex> lk(s->mu);
         const Request *r = s->core->find(id);
+        if (r != nullptr && r->state == boys_serve::State::Failed)
+            return BOYS_ERR_DEVICE;
         if (r == nullptr || r->state != boys_serve::State::Done || ld_dst < r->n)
             return BOYS_ERR_INVALID_ARGUMENT;
         const size_t es = boys_serve::elem_size(r->prec);
@@ -320,9 +374,19 @@ boys_status boys_server_copy_result(boys_server *s, uint64_t id, void *dst, int6
         spitch = (size_t)r->ld * es;
         rows = (size_t)r->n_max + 1;
         const size_t dpitch = (size_t)ld_dst * es;
+        const hipStream_t cs = static_cast<hipStream_t>(stream);
         if (hipMemcpy2DAsync(dst, dpitch, src, spitch, width, rows, hipMemcpyDeviceToDevice,
-                             static_cast<hipStream_t>(stream)) != hipSuccess)
+                             cs) != hipSuccess)
             return BOYS_ERR_DEVICE;
+        // the request's memory must outlive this copy, even if it is released at once
+        void *tok = s->ex.read_token(cs);
+        if (tok == nullptr || !s->core->add_read(id, tok)) {
+            if (tok != nullptr)
+                s->ex.read_free(tok);
+            // no event to track the copy: let it finish before returning
+            if (hipStreamSynchronize(cs) != hipSuccess)
+                return BOYS_ERR_DEVICE;
+        }
     }
     return BOYS_OK;
 }
@@ -359,6 +423,7 @@ boys_status boys_server_get_stats(boys_server *s, boys_server_stats *out)
     out->bytes_in_use = st.bytes_in_use;
     out->max_bytes_in_use = st.max_bytes_in_use;
     out->device_errors = s->ex.errors.load();
+    out->failed = st.failed;
     return BOYS_OK;
 }
 

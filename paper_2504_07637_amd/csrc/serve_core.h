@@ -12,10 +12,17 @@
 //     overlap on the device; requests that arrive while others run join the next batch
 //     (continuous batching);
 //   * marks a batch's requests complete when the executor reports the slot done, and
-//     keeps each result in the pool until the client releases it.
+//     keeps each result in the pool until the client releases it;
+//   * fails a batch's requests, instead of completing them, when its launch could not be
+//     enqueued or its completion reports a device error: a failed request is reported by
+//     poll like a completed one, has no result, and is released like one (no retries);
+//   * keeps a released request's memory allocated until every read of its result that
+//     the client enqueued through the server (a "read token", an event on the client's
+//     stream) has completed, so that a later request cannot overwrite a result that is
+//     still being copied out.
 // The executor is a template parameter: the library uses a HIP executor (streams, events,
-// the persistent batched kernel); the tests drive the same core with a fake executor on a
-// simulated clock.
+// the batched kernel); the tests drive the same core with a fake executor on a simulated
+// clock, which can also inject failed launches and failed completions.
 #pragma once
 
 #include <algorithm>
@@ -104,7 +111,11 @@ class Pool {
     std::map<uint64_t, uint64_t> used_;
 };
 
-enum class State : int { Queued = 0, Admitted = 1, Launched = 2, Done = 3 };
+enum class State : int { Queued = 0, Admitted = 1, Launched = 2, Done = 3, Failed = 4,
+                         Releasing = 5 };
+
+// what the executor reports for a slot
+enum class SlotStatus : int { Running = 0, Done = 1, Failed = 2 };
 
 struct Request {
     uint64_t id = 0;
@@ -118,6 +129,7 @@ struct Request {
     uint64_t bytes = 0;    // whole footprint
     int slot = -1;
     State state = State::Queued;
+    std::vector<void *> reads;  // executor tokens of enqueued reads of the result
     double t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
 };
 
@@ -147,6 +159,7 @@ inline uint64_t footprint(int64_t n, int32_t n_max, int32_t prec)
 
 struct Stats {
     uint64_t submitted = 0, admitted = 0, launched = 0, completed = 0, released = 0;
+    uint64_t failed = 0;  // requests whose batch failed (also counted in completed)
     uint64_t batches = 0;
     uint64_t queued_now = 0, admitted_now = 0, inflight_now = 0;
     uint64_t max_queued = 0, max_inflight_requests = 0;
@@ -154,8 +167,11 @@ struct Stats {
 };
 
 // Exec must provide:
-//   bool done(int slot)                                   -- the slot's last batch finished
-//   bool launch(int slot, const std::vector<Request*>&)   -- enqueue a batch on the slot
+//   SlotStatus status(int slot)                           -- the slot's last batch: running,
+//                                                            finished, or failed on the device
+//   bool launch(int slot, const std::vector<Request*>&)   -- enqueue a batch on the slot; on
+//                                                            false nothing of it is pending
+//   bool read_done(void *token), void read_free(void *token) -- read tokens (see above)
 //   int64_t tile_args() const, int64_t max_tiles() const  -- per-batch tile capacity
 template <class Exec>
 class Core {
@@ -193,20 +209,29 @@ class Core {
         return 0;
     }
 
-    // poll completions, admit by memory, launch on free slots
+    // poll completions and pending reads, admit by memory, launch on free slots
     void step(double now)
     {
         for (int s = 0; s < slots_; ++s) {
-            if (!busy_[s].empty() && ex_->done(s)) {
-                for (uint64_t id : busy_[s]) {
-                    Request &r = reqs_[id];
-                    r.state = State::Done;
-                    r.t_done = now;
-                    completed_.push_back(id);
-                    ++st_.completed;
-                    --inflight_;
-                }
-                busy_[s].clear();
+            if (busy_[s].empty())
+                continue;
+            const SlotStatus ss = ex_->status(s);
+            if (ss == SlotStatus::Running)
+                continue;
+            for (uint64_t id : busy_[s]) {
+                finish(reqs_[id], ss == SlotStatus::Done ? State::Done : State::Failed, now);
+                --inflight_;
+            }
+            busy_[s].clear();
+        }
+        for (auto it = releasing_.begin(); it != releasing_.end();) {
+            Request &r = reqs_[*it];
+            drop_finished_reads(r);
+            if (r.reads.empty()) {
+                free_request(*it);
+                it = releasing_.erase(it);
+            } else {
+                ++it;
             }
         }
         while (!queue_.empty()) {
@@ -236,11 +261,15 @@ class Core {
                 admitted_.pop_front();
             }
             if (!ex_->launch(s, batch)) {
-                // put them back at the front, in order, and stop launching this step
-                for (auto it = batch.rbegin(); it != batch.rend(); ++it)
-                    admitted_.push_front((*it)->id);
+                // the batch fails as a whole (no retry: a launch that failed once, for a
+                // reason the core cannot see, would most likely fail again); the slot
+                // stays free, since the executor left nothing of the batch pending
+                for (Request *r : batch) {
+                    r->t_launch = now;
+                    finish(*r, State::Failed, now);
+                }
                 launch_failures_++;
-                break;
+                continue;
             }
             for (Request *r : batch) {
                 r->state = State::Launched;
@@ -273,24 +302,43 @@ class Core {
         return it == reqs_.end() ? nullptr : &it->second;
     }
 
-    // only completed requests can be released; frees their device memory
-    bool release(uint64_t id)
+    // record a read of a completed request's result enqueued by the client (the token
+    // is the executor's); false if the request is not completed or was released
+    bool add_read(uint64_t id, void *token)
     {
         auto it = reqs_.find(id);
         if (it == reqs_.end() || it->second.state != State::Done)
             return false;
-        pool_.release(it->second.off);
-        reqs_.erase(it);
-        ++st_.released;
-        st_.bytes_in_use = pool_.in_use();
+        it->second.reads.push_back(token);
         return true;
     }
 
-    // nothing admitted and waiting for a slot, nothing running, and the queue is empty
-    // or its head does not fit the free memory (only releases by the client can admit it)
+    // only completed (or failed) requests can be released; their device memory is freed
+    // at once, or, while reads of the result are pending, once the last of them completes
+    bool release(uint64_t id)
+    {
+        auto it = reqs_.find(id);
+        if (it == reqs_.end() ||
+            (it->second.state != State::Done && it->second.state != State::Failed))
+            return false;
+        Request &r = it->second;
+        ++st_.released;
+        drop_finished_reads(r);
+        if (r.reads.empty()) {
+            free_request(id);
+        } else {
+            r.state = State::Releasing;
+            releasing_.push_back(id);
+        }
+        return true;
+    }
+
+    // nothing admitted and waiting for a slot, nothing running, no released memory
+    // waiting for reads, and the queue is empty or its head does not fit the free memory
+    // (only releases by the client can admit it)
     bool quiescent() const
     {
-        if (!admitted_.empty())
+        if (!admitted_.empty() || !releasing_.empty())
             return false;
         for (auto &b : busy_)
             if (!b.empty())
@@ -303,7 +351,7 @@ class Core {
 
     bool idle() const
     {
-        if (!queue_.empty() || !admitted_.empty())
+        if (!queue_.empty() || !admitted_.empty() || !releasing_.empty())
             return false;
         for (auto &b : busy_)
             if (!b.empty())
@@ -325,6 +373,38 @@ class Core {
     uint64_t launch_failures() const { return launch_failures_; }
 
   private:
+    void finish(Request &r, State st, double now)
+    {
+        r.state = st;
+        r.t_done = now;
+        completed_.push_back(r.id);
+        ++st_.completed;
+        if (st == State::Failed)
+            ++st_.failed;
+    }
+
+    void drop_finished_reads(Request &r)
+    {
+        auto &v = r.reads;
+        for (size_t k = 0; k < v.size();) {
+            if (ex_->read_done(v[k])) {
+                ex_->read_free(v[k]);
+                v[k] = v.back();
+                v.pop_back();
+            } else {
+                ++k;
+            }
+        }
+    }
+
+    void free_request(uint64_t id)
+    {
+        auto it = reqs_.find(id);
+        pool_.release(it->second.off);
+        reqs_.erase(it);
+        st_.bytes_in_use = pool_.in_use();
+    }
+
     Pool pool_;
     int slots_;
     std::vector<std::vector<uint64_t>> busy_;
@@ -335,6 +415,7 @@ class Core {
     std::deque<uint64_t> queue_;
     std::deque<uint64_t> admitted_;
     std::deque<uint64_t> completed_;
+    std::vector<uint64_t> releasing_;
     uint64_t inflight_ = 0;
     uint64_t launch_failures_ = 0;
     Stats st_;

@@ -9,7 +9,11 @@ arguments, keeps submitted host buffers alive until completion, and measures.
     ...
     for rid in srv.poll():
         out = srv.fetch(rid)          # (n_max+1, n) tensor on the device (a copy)
-        srv.release(rid)
+        srv.release(rid)              # safe at once: the server keeps the memory until
+                                      # the copy enqueued by fetch has completed
+
+A request whose batch failed on the device is reported by poll too; fetch and times then
+raise BoysError with status BOYS_ERR_DEVICE (release it like any other).
 """
 from __future__ import annotations
 
@@ -68,7 +72,8 @@ class Server:
         return ts.value, td.value
 
     def fetch(self, rid: int, stream=None):
-        """A device copy of a completed request's output, shape (n_max+1, n)."""
+        """A device copy of a completed request's output, shape (n_max+1, n), enqueued on
+        `stream` (default: the current stream).  The request may be released right away."""
         import torch
         _, n, n_max, code = self._live[rid]
         dt = torch.float32 if code in (_lib.FP32, _lib.FP32X, _lib.FP32S) else torch.float64

@@ -49,6 +49,16 @@ def test_argument_errors_are_reported_before_any_launch():
     assert lib.boys_eval(fake, 10, -1, fake, 10, L.FP64, None) == L.ERR_UNSUPPORTED_NMAX
     big = lib.boys_max_nmax(L.FP64) + 1
     assert lib.boys_eval(fake, 10, big, fake, 10, L.FP64, None) == L.ERR_UNSUPPORTED_NMAX
+    # row selection: a non-empty mask of orders 0..n_max; the output holds popcount rows
+    R64 = ctypes.c_uint64
+    assert lib.boys_eval_rows(fake, 10, 4, R64(0), fake, 10, L.FP64, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eval_rows(fake, 10, 4, R64(1 << 5), fake, 10, L.FP64, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eval_rows(fake, 10, 4, R64(3), fake, 9, L.FP64, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eval_rows(None, 10, 4, R64(3), fake, 10, L.FP64, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eval_rows(fake, 10, 4, R64(3), fake, 10, 7, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eval_rows(fake, 10, big, R64(3), fake, 10, L.FP64, None) == L.ERR_UNSUPPORTED_NMAX
+    assert lib.boys_eval_rows(fake, 10, -1, R64(1), fake, 10, L.FP64, None) == L.ERR_UNSUPPORTED_NMAX
+    assert lib.boys_eval_rows(None, 0, 16, R64((1 << 16) | 1), None, 0, L.FP32, None) == L.OK
     # the two-approximation option: 0 <= n_bar < n_max <= the binary64 maximum
     top = lib.boys_max_nmax(L.FP64)
     assert lib.boys_eval_split(fake, 10, 4, 4, fake, 10, None) == L.ERR_UNSUPPORTED_NMAX

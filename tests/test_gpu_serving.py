@@ -1,15 +1,18 @@
 """GPU: the serving loop (boys_server_*) under a Poisson stream of requests.
 
 Each checked request's result in the mix equals, bit for bit, boys_eval on the same
-arguments alone (the tolerance is 0: the batched launch runs the same kernels); every
-request completes; the device budget is respected; a small budget makes requests wait.
+arguments alone and, for a sample, the CPU oracle (the tolerance is 0: the batched launch
+runs the same kernels); every request completes; the device budget is respected; a small
+budget makes requests wait; a result fetched and released at once, without any
+synchronisation, is intact even when later requests reuse its memory.
 """
 import sys
 
 import numpy as np
 import pytest
 
-from gpu_common import require_gpu
+from gpu_common import require_gpu, same_bits
+from oracle import oracle as orc
 
 pytestmark = pytest.mark.gpu
 
@@ -34,6 +37,7 @@ def test_serving_results_equal_solo(budget_mb, streams):
              else pr) for i, (t, ln, nm, pr) in enumerate(reqs)]
     checked = []
     bad = []
+    oracle_bad = []
     srv = None
 
     def check(i, rid):
@@ -49,6 +53,11 @@ def test_serving_results_equal_solo(budget_mb, streams):
         checked.append(i)
         if not torch.equal(got, solo):
             bad.append((i, ln, nm, pr))
+        if i % 51 == 0:
+            # directly against the oracle too
+            xh = pool[off:off + ln].numpy()
+            if not same_bits(got.cpu().numpy(), _oracle(xh, nm, pr)).all():
+                oracle_bad.append((i, ln, nm, pr))
 
     _say(f"[serving] {len(reqs)} requests, budget {budget_mb} MiB, {streams} streams")
     with serving.Server(budget_bytes=budget_mb << 20, streams=streams) as srv:
@@ -60,7 +69,47 @@ def test_serving_results_equal_solo(budget_mb, streams):
         if budget_mb == 64:
             assert st["max_queued"] > 0
         assert len(checked) == len(range(0, len(reqs), 17)) and not bad, bad[:5]
-        assert st["bytes_in_use"] == 0
+        assert not oracle_bad, oracle_bad[:5]
+        assert st["bytes_in_use"] == 0 and st["failed"] == 0
+
+
+def _oracle(x, n, code):
+    return (orc.approx_f64(x, n) if code == 0 else orc.approx_mixed(x, n) if code == 1
+            else orc.approx_f64(x, n + 1)[: n + 1] if code == 2 else orc.approx_f32x(x, n)
+            if code == 3 else orc.approx_single(x, n))
+
+
+def test_fetch_then_release_without_synchronisation():
+    # Every completed request is fetched (a copy enqueued on the current stream) and
+    # released at once, with no synchronisation, under a budget so small that later
+    # requests reuse the same memory while the copies may still be pending; every 7th
+    # fetched copy is checked against the oracle at the end.
+    torch = require_gpu()
+    from paper_2504_07637_amd import inputs, serving
+    pool = serving.argument_pool(1 << 21, seed=6)
+    P = pool.numel()
+    reqs = inputs.serving_requests(rate=20000.0, duration=0.1, seed=66)
+    reqs = [(t, min(ln, 1 << 16), nm, pr) for t, ln, nm, pr in reqs]
+    fetched = {}
+    srv = None
+
+    def grab(i, rid):
+        if i % 7 == 0:
+            fetched[i] = srv.fetch(rid)
+
+    _say(f"[serving] fetch+release, {len(reqs)} requests, 24 MiB budget")
+    with serving.Server(budget_bytes=24 << 20, streams=2) as srv:
+        serving.run_poisson(srv, reqs, pool, on_done=grab)
+        st = srv.stats()
+    torch.cuda.synchronize()
+    assert st["max_queued"] > 0 and st["failed"] == 0 and st["bytes_in_use"] == 0
+    bad = []
+    for i, got in fetched.items():
+        _, ln, nm, pr = reqs[i]
+        off = (i * 1000003) % (P - ln)
+        if not same_bits(got.cpu().numpy(), _oracle(pool[off:off + ln].numpy(), nm, pr)).all():
+            bad.append(i)
+    assert len(fetched) == len(range(0, len(reqs), 7)) and not bad, bad[:5]
 
 
 def test_serving_refuses_what_can_never_fit():

@@ -4,7 +4,10 @@ Compiles tests/native/serve_core_harness.cpp with g++ and checks: the pool never
 overlaps or leaks and coalesces back to one block; admission follows arrival order and
 never exceeds the budget; every request completes once; batches overlap on different
 slots, and requests that arrive while a batch runs are launched before it ends
-(continuous batching); requests that can never fit are refused at submission.
+(continuous batching); requests that can never fit are refused at submission; a failed
+launch or a failed completion fails exactly its batch's requests, once, with no retry; a
+released request keeps its memory until the reads of its result enqueued before the
+release have completed.
 """
 import ctypes
 import os
@@ -31,6 +34,10 @@ def harness(tmp_path_factory):
                           ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, dp, ip, ip,
                           lp, ip, ip, ip]
     L.pool_fuzz.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64]
+    L.sim_failures.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ip,
+                               ctypes.c_int, ip, ctypes.c_int, ip, ip, ip]
+    L.sim_pending_read.argtypes = [ctypes.c_int64, ctypes.c_double, dp,
+                                   ctypes.POINTER(ctypes.c_uint64), ip]
     return L
 
 
@@ -135,3 +142,59 @@ def test_policy_core_under_address_and_undefined_behaviour_sanitizers(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300, env=env)
     assert r.returncode == 0, r.stdout + r.stderr
     assert r.stdout.startswith("ok:"), r.stdout
+
+
+def _failures(L, nreq, n, slots, max_batch, fail_launch, fail_done):
+    ip = ctypes.POINTER(ctypes.c_int)
+    fl = np.ascontiguousarray(fail_launch, dtype=np.int32)
+    fd = np.ascontiguousarray(fail_done, dtype=np.int32)
+    st = np.zeros(nreq, dtype=np.int32)
+    rp = np.zeros(nreq, dtype=np.int32)
+    failed = ctypes.c_int()
+    launches = L.sim_failures(nreq, n, slots, max_batch, fl.ctypes.data_as(ip), fl.size,
+                              fd.ctypes.data_as(ip), fd.size, st.ctypes.data_as(ip),
+                              rp.ctypes.data_as(ip), ctypes.byref(failed))
+    return launches, st, rp, failed.value
+
+
+DONE, FAILED = 3, 4
+
+
+def test_failed_launches_and_completions_fail_their_batch_once(harness):
+    # requests 1e-4 s apart, each served long before the next arrives: launch attempt k
+    # carries request k alone.  Attempts 0 and 3 fail to launch; of the launched batches,
+    # numbers 1 and 5 (requests 2 and 7) report a device error at completion.
+    launches, st, rp, failed = _failures(harness, 40, 1000, 2, 4, [0, 3], [1, 5])
+    assert launches == 40                      # no attempt was repeated
+    assert np.all(rp == 1)                     # each request reported exactly once
+    want = np.full(40, DONE)
+    want[[0, 2, 3, 7]] = FAILED
+    assert np.array_equal(st, want), np.nonzero(st != want)
+    assert failed == 4
+
+
+def test_failures_inside_coalesced_batches(harness):
+    # long requests pile up behind each other, so launches carry several requests: a failed
+    # launch or completion fails all of them, the rest complete, nothing is retried and the
+    # pool empties
+    launches, st, rp, failed = _failures(harness, 200, 3_000_000, 3, 8, [0, 3, 9], [1, 5, 6])
+    assert launches > 0, launches
+    assert launches < 200                      # requests were coalesced
+    assert np.all(rp == 1)
+    assert failed == int(np.sum(st == FAILED)) and failed >= 6
+    assert np.all((st == DONE) | (st == FAILED))
+
+
+def test_release_waits_for_pending_reads(harness):
+    # A's result is being read until t = 10 ms; A is released at once.  B needs A's memory,
+    # so B is admitted only after the read has completed, and A's bytes stay in use meanwhile
+    n = 100000
+    tb = ctypes.c_double()
+    in_use = ctypes.c_uint64()
+    freed = ctypes.c_int()
+    rc = harness.sim_pending_read(n, 0.01, ctypes.byref(tb), ctypes.byref(in_use),
+                                  ctypes.byref(freed))
+    assert rc == 0, rc
+    assert tb.value >= 0.01
+    assert in_use.value == footprint(n, 4, 0)
+    assert freed.value == 2
