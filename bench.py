@@ -13,12 +13,19 @@ Besides the headline the line carries:
                 over its average launch time from HIP events on the launch stream;
                 traffic from the committed rocprofv3 counter summary when it matches
                 the current kernel source, else null;
-  cpu_baseline  the CPU oracle's binary64 evaluation of the same approximant on a
-                bounded prefix of the same workload, on this host's cores;
+  store_reduced a diagnostic, not the headline: the same arguments and n_max = 16
+                arithmetic through boys_eval_rows storing only F_0 and F_16 (24 B per
+                argument), which shows the arithmetic against the VALU roofline;
+  cpu_baseline  the CPU oracle's binary64 evaluation of the same approximant (built
+                -O3 -march=native for this host) on a bounded prefix of the same
+                workload, on this host's cores;
   accuracy      -log2 of the largest relative error per class against the exact
                 oracle on 2^13 sampled arguments (every m);
   latency       p50/p99 of single calls on the small 65,536-argument workload
-                (n_max = 4, binary64), and the batched 8,192-array workload time;
+                (n_max = 4, binary64);
+  batched       the 8,192-array workload: the autotuned plan and the persistent
+                one-launch plan, each labelled with its launch structure, against a
+                roofline combined from every array's bytes and VALU work;
   serving       p50/p99 request latency and sustained values/s of the serving loop
                 under Poisson arrivals at 20,000 requests/s.
 """
@@ -38,9 +45,14 @@ sys.path.insert(0, REPO)
 
 N_ARGS = 1 << 26
 N_MAX = 16
+SR_ROWS = [0, N_MAX]   # the store-reduced diagnostic keeps F_0 and F_16
 SPLIT_NBAR = 8   # the two-approximation option: rows 0..8 from the order-8 approximant
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6   # MI355X binary64 vector peak (an fma counts 2)
+# VALU issue capacity: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at
+# 2.4 GHz (the same figure as the 78.6 TFLOP/s binary64 peak: 1024 x 16 lanes x 2 x 2.4e9)
+VALU_WAVE_INSTR_PER_S = 1024 * 2.4e9 / 4
+VALU_TABLE_FILE = os.path.join(REPO, "profiles", "valu_per_order_integral.json")
 TRAFFIC_FILE = os.path.join(REPO, "profiles", "traffic_boys_f64_n16.json")
 KERNEL_SOURCES = [os.path.join(REPO, "paper_2504_07637_amd", "csrc", f)
                   for f in ("boys_device.h", "boys_kernels.h", "plain_inst.hip", "eri_inst.hip",
@@ -68,9 +80,11 @@ def parse():
                     help="target length of the CPU-baseline sample")
     ap.add_argument("--skip-extras", action="store_true",
                     help="only the headline (for profiling runs)")
-    ap.add_argument("--workload", choices=("boys", "eri"), default="boys",
+    ap.add_argument("--workload", choices=("boys", "eri", "valu-table"), default="boys",
                     help="boys: the headline bulk evaluation (default); eri: the consumer "
-                         "kernel on its own (contracted (ss|ss)^(m) integrals)")
+                         "kernel on its own (contracted (ss|ss)^(m) integrals); valu-table: "
+                         "one plain launch per (class, n_max), binary64 and mixed, n_max "
+                         "0..16, on 2^22 integral arguments (for per-order VALU counters)")
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="first run one elementwise kernel over 1 GiB (1 GiB read, 1 GiB "
                          "written), a dispatch of known traffic for scaling rocprofv3 "
@@ -101,11 +115,27 @@ def timed(torch, fn, steps, warmup):
 
 
 def cpu_model():
+    """The host CPU as lscpu reports it (model name, sockets, cores), else /proc/cpuinfo."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        info = {}
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                info[k.strip()] = v.strip()
+        keys = ("Model name", "Vendor ID", "CPU family", "Model", "Socket(s)",
+                "Core(s) per socket", "Thread(s) per core", "CPU(s)", "CPU max MHz")
+        got = {k: info[k] for k in keys if k in info}
+        if got:
+            return got
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
                 if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                    return {"Model name": line.split(":", 1)[1].strip()}
     except OSError:
         pass
     return None
@@ -115,6 +145,7 @@ def cpu_baseline(x, target_s):
     from oracle import oracle as orc
     os.environ.setdefault("OMP_NUM_THREADS", str(len(os.sched_getaffinity(0))))
     threads = int(os.environ["OMP_NUM_THREADS"])  # what the oracle's OpenMP loops use
+    orc.use_native_build()   # the same C source at -O3 -march=native for this host
     n = 1 << 18
     while True:
         t0 = time.perf_counter()
@@ -123,14 +154,23 @@ def cpu_baseline(x, target_s):
         if dt * 4 > target_s or n * 4 > x.size:
             break
         n *= 4
+    # the oracle's exp(-x) is binary128 expq, rounded once: its share of the time
+    t0 = time.perf_counter()
+    orc.exp_neg(x[:n])
+    dtx = time.perf_counter() - t0
     ne = 1 << 14
     t0 = time.perf_counter()
     orc.exact(x[:ne], N_MAX)
     dte = time.perf_counter() - t0
     return {"value": (N_MAX + 1) * n / dt, "unit": "values/s", "cores": threads,
             "kind": "oracle", "cpu_model": cpu_model(),
+            "build": "gcc -O3 -march=native -fopenmp -ffp-contract=off (schedule static)",
             "sample": f"first {n} arguments of the same 2^26 workload, n_max=16, binary64 "
                       f"approximant oracle (plain C, OpenMP, {dt:.2f} s)",
+            "expq_seconds": round(dtx, 3), "expq_share": round(dtx / dt, 3),
+            "expq_note": "the oracle takes exp(-x) as binary128 expq rounded to binary64 "
+                         "(correct rounding by construction); that alone is expq_share of "
+                         "its time, so this is no tuned CPU code",
             "exact_oracle_values_per_s": (N_MAX + 1) * ne / dte,
             "exact_oracle_sample": f"first {ne} arguments, F_0..F_16 from the definition in "
                                    f"binary128 (OpenMP, {dte:.2f} s)"}
@@ -205,6 +245,67 @@ def latency(torch, boys, inputs):
             "graph_p99_us": round(float(np.percentile(tg, 99)), 2)}
 
 
+def describe_plan(t):
+    """The launch structure a tuning gives (boys_tuning in include/boys.h)."""
+    if t.get("schedule") == 0:
+        return (f"one persistent launch in the plan's graph: {t.get('grid_per_cu')} workgroups "
+                f"of {t.get('block')} threads per CU take {t.get('tile')}-argument tiles from "
+                f"a work counter (after a one-wave kernel that zeroes it)")
+    if t.get("schedule") == 1:
+        return (f"one launch in the plan's graph: one {t.get('block')}-thread workgroup per "
+                f"{t.get('tile')}-argument tile")
+    if t.get("split_nmax"):
+        return (f"two launches in the plan's graph: the store-bound arrays (n_max >= "
+                f"{t['split_nmax']} binary64, >= {t['split_nmax'] + 4} binary32) one "
+                f"256-thread workgroup per 256-argument tile, then the rest one wave per "
+                f"256-argument tile ({t.get('block')}-thread workgroups)")
+    return (f"one launch in the plan's graph: one wave per 256-argument tile "
+            f"({t.get('block')}-thread workgroups)")
+
+
+def valu_table():
+    """Per-(class, n_max) VALU wave instructions per argument on the integral workload,
+    from the committed counter run, if the kernels have not changed since."""
+    try:
+        with open(VALU_TABLE_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    return d if d.get("kernel_hash") == kernel_hash() else None
+
+
+def batch_roofline(plan_spec, ms):
+    """Rooflines of the batch from every array's algorithmic bytes and VALU work (VALU
+    wave instructions per argument of its (class, n_max) by counters):
+      overlapped  max(sum bytes / 8 TB/s, sum VALU / issue capacity): arrays overlap on
+                  the device, so no launch can beat this;
+      per_array   sum over arrays of max(bytes / 8 TB/s, VALU / issue capacity): every
+                  array at its own roofline, one after another."""
+    tab = valu_table()
+    if tab is None:
+        return None
+    per = tab["wave_instructions_per_argument"]
+    tb = tv = tpa = 0.0
+    for l, m, p in plan_spec:
+        cls = "fp64" if p == 0 else "fp32"
+        byt = l * (8 + (m + 1) * (8 if p == 0 else 4))
+        wi = l * per[cls][m]
+        tb += byt / (PEAK_HBM_GBS * 1e9)
+        tv += wi / VALU_WAVE_INSTR_PER_S
+        tpa += max(byt / (PEAK_HBM_GBS * 1e9), wi / VALU_WAVE_INSTR_PER_S)
+    ov = max(tb, tv)
+    return {"hbm_ms": tb * 1e3, "valu_ms": tv * 1e3, "overlapped_bound_ms": ov * 1e3,
+            "per_array_bound_ms": tpa * 1e3, "frac_of_overlapped": ov * 1e3 / ms,
+            "frac_of_per_array": tpa * 1e3 / ms,
+            "source": "algorithmic bytes; VALU wave instructions per argument per (class, "
+                      "n_max) from rocprofv3 counters (" + os.path.basename(VALU_TABLE_FILE) +
+                      "), issue capacity 1024 SIMDs x 2.4 GHz / 4 cycles"}
+
+
+PERSISTENT_SWEEP = [{"schedule": 0, "tile": t, "block": 256, "grid_per_cu": g, "order": 1}
+                    for t in (256, 1024) for g in (2, 4, 5, 8)]
+
+
 def batched(torch, boys, inputs, steps):
     plan_spec = inputs.batch_plan(8192, seed=4)
     total = sum(l for l, _, _ in plan_spec)
@@ -222,6 +323,14 @@ def batched(torch, boys, inputs, steps):
     values = sum(l * (m + 1) for l, m, _ in plan_spec)
     bytes_ = sum(l * (8 + (m + 1) * (8 if p == 0 else 4)) for l, m, p in plan_spec)
     ms = gpu / steps * 1e3
+    # the persistent one-launch schedule over the same arrays and outputs, swept
+    pers = {}
+    for t in PERSISTENT_SWEEP:
+        pp = boys.Plan(xs, nm, pr, tuning=t, outs=plan.outs)
+        _, g = timed(torch, pp.execute, steps, 12)
+        pers[json.dumps(t, sort_keys=True)] = round(g / steps * 1e3, 4)
+        pp.close()
+    pbest = min(pers, key=pers.get)
     # the same arrays as 8,192 separate boys_eval calls into the plan's outputs
     solo = lambda: [boys.boys_eval(xi, m, p, out=o) for xi, m, p, o in zip(xs, nm, pr, plan.outs)]
     solo_wall, solo_gpu = timed(torch, solo, 2, 1)
@@ -236,9 +345,15 @@ def batched(torch, boys, inputs, steps):
     grp_wall, grp_gpu = timed(torch, grouped, steps, 3)
     del gx, go
     res = {"workload": "8,192 arrays, lengths logU[32,65536], n_max U{0..16}, "
-                       "binary64/binary32 alternating, one graph-captured batched launch",
+                       "binary64/binary32 alternating",
+           "plan": describe_plan(best),
            "arguments": total, "ms": round(ms, 4), "values_per_s": values / (gpu / steps),
            "hbm_GBs": bytes_ / (ms * 1e-3) / 1e9, "tuning": best,
+           "roofline": batch_roofline(plan_spec, ms),
+           "persistent": {"plan": describe_plan(json.loads(pbest)), "ms": pers[pbest],
+                          "values_per_s": values / (pers[pbest] * 1e-3),
+                          "tuning": json.loads(pbest), "sweep_ms": pers,
+                          "roofline": batch_roofline(plan_spec, pers[pbest])},
            "solo_calls_ms": round(solo_gpu / 2 * 1e3, 3),
            "batching_gain": round(solo_gpu / 2 / (gpu / steps), 2),
            "grouped_plain_ms": round(grp_gpu / steps * 1e3, 4),
@@ -371,6 +486,17 @@ def main():
         line.update({k: v for k, v in r.items() if k not in line and k != "workload"})
         print(json.dumps(line), flush=True)
         return
+    if args.workload == "valu-table":
+        # one plain launch per (class, n_max): the per-order VALU counters of the batch's
+        # combined roofline are read per dispatch from a rocprofv3 --pmc run of this mode
+        xt = torch.from_numpy(inputs.integral_args(1 << 22, seed=4)).to("cuda")
+        for prec in ("fp64", "fp32"):
+            for m in range(N_MAX + 1):
+                boys.boys_eval(xt, m, prec)
+                torch.cuda.synchronize()
+        print(json.dumps({"valu_table": "fp64 then fp32, n_max 0..16, 2^22 integral "
+                                        "arguments, one launch each"}), flush=True)
+        return
     x = inputs.integral_args(N_ARGS, seed=2)
     xd = torch.from_numpy(x).to("cuda")
     out64 = torch.empty((N_MAX + 1, N_ARGS), dtype=torch.float64, device="cuda")
@@ -386,6 +512,14 @@ def main():
                             args.steps, args.warmup)
     wall_sp, gpu_sp = timed(torch, lambda: boys.boys_eval_split(xd, N_MAX, SPLIT_NBAR, out=out64),
                             args.steps, args.warmup)
+    # the store-reduced diagnostic: the same evaluation, only F_0 and F_16 stored
+    sr = {}
+    for prec, dt, es in (("fp64", torch.float64, 8), ("fp32", torch.float32, 4)):
+        o = torch.empty((len(SR_ROWS), N_ARGS), dtype=dt, device="cuda")
+        _, g = timed(torch, lambda: boys.boys_eval_rows(xd, N_MAX, SR_ROWS, prec, out=o),
+                     args.steps, args.warmup)
+        sr[prec] = (g / args.steps, (8 + es * len(SR_ROWS)) * N_ARGS)
+        del o
     values = (N_MAX + 1) * N_ARGS
     ms64 = wall64 / args.steps * 1e3
     v64 = values * args.steps / wall64
@@ -413,10 +547,14 @@ def main():
                    "n_args": N_ARGS, "n_max": N_MAX},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic_for(khash),
-                     "valu": valu_for(khash, "k_plain<0, 16>", launch_s),
+                     "valu": valu_for(khash, "k_plain<0, 16, false>", launch_s),
                      "kernel": "k_plain<FP64,16>", "launch_ms": launch_s * 1e3,
                      "alg_bytes_per_launch": alg_bytes, "kernel_hash": khash},
         "fp32": {"value": v32, "unit": "values/s", "ms_per_step": wall32 / args.steps * 1e3,
+                 "class": "mixed: u/v, Q~, W and the recursion in binary32, x + W and "
+                          "c_n/G^(n+1/2) in binary64; exp(-x) and the past-cut-off chain "
+                          "(long-range limit) are also evaluated in binary64 and rounded to "
+                          "binary32, beyond a strict reading of binary64 for the power only",
                  "speedup_vs_fp64": v32 / v64,
                  "launch_ms": gpu32 / args.steps * 1e3,
                  "hbm_GBs": (8 + 4 * (N_MAX + 1)) * N_ARGS / (gpu32 / args.steps) / 1e9},
@@ -435,6 +573,18 @@ def main():
                   "launch_ms": gpu32s / args.steps * 1e3,
                   "hbm_GBs": (8 + 4 * (N_MAX + 1)) * N_ARGS / (gpu32s / args.steps) / 1e9},
     }
+    res["store_reduced"] = {
+        "kind": "diagnostic, not the headline: the same 2^26 arguments and n_max = 16 "
+                "arithmetic (boys_eval_rows), only F_0 and F_16 stored",
+        "rows": SR_ROWS}
+    for prec, (t, byt) in sr.items():
+        kern = f"k_plain<{0 if prec == 'fp64' else 1}, {N_MAX}, true>"
+        res["store_reduced"][prec] = {
+            "launch_ms": t * 1e3, "arguments_per_s": N_ARGS / t,
+            "alg_bytes_per_launch": byt, "hbm_GBs": byt / t / 1e9,
+            "hbm_frac": byt / t / 1e9 / PEAK_HBM_GBS,
+            "speedup_vs_full_store": (gpu64 if prec == "fp64" else gpu32) / args.steps / t,
+            "kernel": kern, "valu": valu_for(khash, kern, t)}
     # measured HBM figures on this device: one write stream (fill) and a read+write copy
     wall_f, gpu_f = timed(torch, lambda: out64.fill_(1.0), 5, 2)
     fill_GBs = out64.numel() * 8 / (gpu_f / 5) / 1e9

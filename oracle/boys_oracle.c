@@ -525,6 +525,7 @@ int oracle_boys_approx_q(const double *x, int64_t count, const double *recx, dou
 /* exp(-x) as used by both approximant evaluators, for direct checks */
 int oracle_exp_neg(const double *x, int64_t count, double *out)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < count; ++i)
         out[i] = exp_rn(-x[i]);
     return 0;

@@ -39,50 +39,68 @@ SRC = os.path.join(HERE, "boys_oracle.c")
 DATASET = os.path.join(REPO, "paper_2504_07637_amd", "data", "boys_coeffs.txt")
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain IEEE arithmetic, no contraction)."""
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
-        cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-               "-fno-fast-math", "-o", LIB_PATH + ".tmp", SRC, "-lquadmath", "-lm"]
+NATIVE_LIB_PATH = os.path.join(HERE, "liboracle_native.so")
+
+
+def build(force: bool = False, native: bool = False) -> str:
+    """Compile the oracle with gcc (plain IEEE arithmetic, no contraction).  native: the
+    same source at -O3 -march=native for the host it runs on (the timed CPU baseline; the
+    same IEEE operations, since nothing is contracted)."""
+    path = NATIVE_LIB_PATH if native else LIB_PATH
+    opt = ["-O3", "-march=native"] if native else ["-O2"]
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC):
+        tmp = f"{path}.tmp{os.getpid()}"  # concurrent builders each write their own file
+        cmd = ["gcc", *opt, "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", "-o", tmp, SRC, "-lquadmath", "-lm"]
         subprocess.check_call(cmd)
-        os.replace(LIB_PATH + ".tmp", LIB_PATH)
-    return LIB_PATH
+        os.replace(tmp, path)
+    return path
 
 
 _lib = None
 
 
+def use_native_build():
+    """Build the same source at -O3 -march=native for this host and route every later
+    call through it (the CPU-baseline timing)."""
+    global _lib
+    _lib = _load(build(force=True, native=True))
+
+
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(LIB_PATH)
-        dp = ctypes.POINTER(ctypes.c_double)
-        fp = ctypes.POINTER(ctypes.c_float)
-        i64 = ctypes.c_int64
-        L.oracle_boys_exact.argtypes = [dp, i64, ctypes.c_int, dp, dp]
-        L.oracle_boys_exact_one.argtypes = [dp, i64, ctypes.c_int, dp, dp]
-        L.oracle_boys_approx_f64.argtypes = [dp, i64, dp, ctypes.c_int, dp, i64]
-        L.oracle_boys_approx_mixed.argtypes = [dp, i64, dp, ctypes.c_int, fp, i64]
-        L.oracle_boys_approx_f64r.argtypes = [dp, i64, dp, ctypes.c_int, dp, i64]
-        L.oracle_boys_approx_f64r.restype = ctypes.c_int
-        L.oracle_boys_approx_single.argtypes = [dp, i64, dp, ctypes.c_int, fp, i64]
-        L.oracle_boys_approx_single.restype = ctypes.c_int
-        L.oracle_kappa32.argtypes = [ctypes.c_int]
-        L.oracle_kappa32.restype = ctypes.c_float
-        L.oracle_boys_approx_q.argtypes = [dp, i64, dp, dp, dp]
-        L.oracle_exp_neg.argtypes = [dp, i64, dp]
-        ip = ctypes.POINTER(ctypes.c_int32)
-        L.oracle_eri_ssss.argtypes = [dp, ctypes.c_int, dp, i64, ip, ctypes.c_int32, dp, i64, ip,
-                                      ctypes.c_int32, dp, i64]
-        L.oracle_eri_ssss.restype = ctypes.c_int
-        L.oracle_eri_prefactor.argtypes = []
-        L.oracle_eri_prefactor.restype = ctypes.c_double
-        for f in (L.oracle_boys_exact, L.oracle_boys_exact_one, L.oracle_boys_approx_f64, L.oracle_boys_approx_mixed,
-                  L.oracle_boys_approx_q, L.oracle_exp_neg):
-            f.restype = ctypes.c_int
-        _lib = L
+        _lib = _load(build())
     return _lib
+
+
+def _load(path):
+    L = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    fp = ctypes.POINTER(ctypes.c_float)
+    i64 = ctypes.c_int64
+    L.oracle_boys_exact.argtypes = [dp, i64, ctypes.c_int, dp, dp]
+    L.oracle_boys_exact_one.argtypes = [dp, i64, ctypes.c_int, dp, dp]
+    L.oracle_boys_approx_f64.argtypes = [dp, i64, dp, ctypes.c_int, dp, i64]
+    L.oracle_boys_approx_mixed.argtypes = [dp, i64, dp, ctypes.c_int, fp, i64]
+    L.oracle_boys_approx_f64r.argtypes = [dp, i64, dp, ctypes.c_int, dp, i64]
+    L.oracle_boys_approx_f64r.restype = ctypes.c_int
+    L.oracle_boys_approx_single.argtypes = [dp, i64, dp, ctypes.c_int, fp, i64]
+    L.oracle_boys_approx_single.restype = ctypes.c_int
+    L.oracle_kappa32.argtypes = [ctypes.c_int]
+    L.oracle_kappa32.restype = ctypes.c_float
+    L.oracle_boys_approx_q.argtypes = [dp, i64, dp, dp, dp]
+    L.oracle_exp_neg.argtypes = [dp, i64, dp]
+    ip = ctypes.POINTER(ctypes.c_int32)
+    L.oracle_eri_ssss.argtypes = [dp, ctypes.c_int, dp, i64, ip, ctypes.c_int32, dp, i64, ip,
+                                  ctypes.c_int32, dp, i64]
+    L.oracle_eri_ssss.restype = ctypes.c_int
+    L.oracle_eri_prefactor.argtypes = []
+    L.oracle_eri_prefactor.restype = ctypes.c_double
+    for f in (L.oracle_boys_exact, L.oracle_boys_exact_one, L.oracle_boys_approx_f64, L.oracle_boys_approx_mixed,
+              L.oracle_boys_approx_q, L.oracle_exp_neg):
+        f.restype = ctypes.c_int
+    return L
 
 
 def _dp(a):
