@@ -5,7 +5,7 @@
 // Compiled once per (B, S, K) with -DBOYS_BUCKET=<B> -DBOYS_SCHED=<S> -DBOYS_K=<K>.
 #include <algorithm>
 
-#include "boys_kernels.h"
+#include "boys_batched.h"
 
 #if !defined(BOYS_BUCKET) || !defined(BOYS_SCHED) || !defined(BOYS_K)
 #error "compile with -DBOYS_BUCKET=<bucket> -DBOYS_SCHED=<0, 1, 2> -DBOYS_K=<tile factor>"

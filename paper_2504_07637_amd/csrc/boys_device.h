@@ -484,48 +484,6 @@ __host__ __device__ __forceinline__ void eval_split(double x, int nbar,
 }
 
 // ---------------------------------------------------------------------------------
-// A consumer of F_m: the contracted (ss|ss)^(m) auxiliary integrals of one bra and one
-// ket contracted pair of s-type Gaussians; the arithmetic and its order are those that
-// the declaration of boys_eri_ssss states.
-
-struct PairList {
-    const double *p, *px, *py, *pz, *w;  // primitive pairs: p, product centre P, weight
-    const int32_t *start;                // contracted pair c: primitive pairs [start[c], start[c+1])
-    int32_t count;
-};
-
-template <int N>
-__host__ __device__ __forceinline__ void eri_ssss_one(const PairList &bra, const PairList &ket,
-                                                      int32_t i, int32_t j, double K,
-                                                      const double2 *__restrict__ tab,
-                                                      double (&acc)[N + 1])
-{
-#pragma unroll
-    for (int m = 0; m <= N; ++m)
-        acc[m] = 0.0;
-    const int32_t a1 = bra.start[i + 1], b0 = ket.start[j], b1 = ket.start[j + 1];
-    for (int32_t a = bra.start[i]; a < a1; ++a) {
-        const double p = bra.p[a], px = bra.px[a], py = bra.py[a], pz = bra.pz[a];
-        const double wa = bra.w[a];
-        for (int32_t b = b0; b < b1; ++b) {
-            const double q = ket.p[b];
-            const double pq = p * q;
-            const double spq = p + q;
-            const double rho = pq / spq;
-            const double dx = px - ket.px[b], dy = py - ket.py[b], dz = pz - ket.pz[b];
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            const double T = rho * r2;
-            const double s = (wa * ket.w[b]) * (K / (pq * __builtin_sqrt(spq)));
-            double F[N + 1];
-            eval_f64<N>(T, tab, F);
-#pragma unroll
-            for (int m = 0; m <= N; ++m)
-                acc[m] = __builtin_fma(s, F[m], acc[m]);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------------
 // F_0..F_N for one argument, mixed binary32/binary64 class
 
 template <int N>

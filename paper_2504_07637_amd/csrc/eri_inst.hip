@@ -2,7 +2,7 @@
 #include <array>
 #include <utility>
 
-#include "boys_kernels.h"
+#include "boys_eri.h"
 
 namespace {
 

@@ -130,9 +130,15 @@ def test_kernel_hash_ignores_comments(tmp_path, monkeypatch):
     import bench
     src = tmp_path / "k.h"
     src.write_text("int a; // one\n\nint b;\n")
-    monkeypatch.setattr(bench, "KERNEL_SOURCES", [str(src)])
+    monkeypatch.setattr(bench, "_CSRC", str(tmp_path))
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", {"plain": ("k.h",), "eri": ("k.h", "e.h")})
+    (tmp_path / "e.h").write_text("int e;\n")
     h1 = bench.kernel_hash()
+    he = bench.kernel_hash("eri")
     src.write_text("int a; // another comment\n// a comment line\nint b;\n")
     assert bench.kernel_hash() == h1
+    # a change to one family's own source leaves the others' hashes alone
+    (tmp_path / "e.h").write_text("int e2;\n")
+    assert bench.kernel_hash() == h1 and bench.kernel_hash("eri") != he
     src.write_text("int a;\nint c;\n")
     assert bench.kernel_hash() != h1
