@@ -39,6 +39,7 @@
 #ifndef BOYS_H
 #define BOYS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -75,7 +76,9 @@ typedef enum {
     BOYS_ERR_INVALID_ARGUMENT = 1, /* null pointer with n > 0, ld_out < n, bad precision, count < 0 */
     BOYS_ERR_UNSUPPORTED_NMAX = 2, /* n_max < 0 or n_max > boys_max_nmax(precision) */
     BOYS_ERR_OUT_OF_MEMORY = 3,    /* a plan or batch could not get its device buffers */
-    BOYS_ERR_DEVICE = 4            /* a HIP call or kernel launch failed */
+    BOYS_ERR_DEVICE = 4,           /* a HIP call or kernel launch failed */
+    BOYS_ERR_TOO_LARGE = 5         /* the batch's tables exceed the fixed scratch array of
+                                      boys_eval_batched_noalloc */
 } boys_status;
 
 /*
@@ -196,6 +199,25 @@ typedef struct {
  * call, synchronising stream before the free); use a plan for repeated batches.
  */
 boys_status boys_eval_batched(const boys_array *arrays, int32_t count, void *stream);
+
+/*
+ * boys_eval_batched without any allocation, for callers that cannot allocate device
+ * memory (allocation-free serving loops, harnesses that forbid hipMalloc): the same
+ * kernels, the same default schedule and results equal bit for bit to those of
+ * boys_eval_batched, with the descriptor and tile tables in a fixed device array of the
+ * library (BOYS_NOALLOC_SCRATCH_BYTES per device, held until the process ends) instead of
+ * buffers allocated per call.  No hipMalloc, hipFree or other allocating call is made.
+ * Limit: 256 + 40 * count bytes (rounded up to 256) + 8 bytes per 256-argument tile of
+ * every array must fit in the array (about 2.6e8 arguments in total for a few thousand
+ * arrays); larger batches return BOYS_ERR_TOO_LARGE before anything is enqueued.
+ * The call uploads the tables on stream from a static host staging area, enqueues the
+ * kernels and synchronises stream before it returns (work already on stream is waited
+ * for too).  The library serialises these calls (one staging area, one array per device,
+ * each call overwriting the previous call's tables), so calls from several threads do
+ * not race but do not overlap either.  Not usable under stream capture (it synchronises).
+ */
+#define BOYS_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+boys_status boys_eval_batched_noalloc(const boys_array *arrays, int32_t count, void *stream);
 
 /*
  * Plans: a schedule (tiles in the tuning's order, descriptor and tile tables in

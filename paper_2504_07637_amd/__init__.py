@@ -17,7 +17,7 @@ import ctypes
 from . import _lib
 from ._lib import FP32, FP32S, FP32X, FP64, FP64_PLUS, BoysArray, BoysError, BoysTuning
 
-__all__ = ["boys_eval", "boys_eval_rows", "boys_eval_split", "boys_eri_ssss", "boys_eval_batched", "Plan", "autotune", "max_nmax", "cutoff",
+__all__ = ["boys_eval", "boys_eval_rows", "boys_eval_split", "boys_eri_ssss", "boys_eval_batched", "boys_eval_batched_noalloc", "Plan", "autotune", "max_nmax", "cutoff",
            "precision_code", "padded_ld", "empty_out", "BoysError", "FP64", "FP32", "FP64_PLUS",
            "FP32X", "FP32S"]
 
@@ -268,6 +268,19 @@ def boys_eval_batched(xs, n_maxs, precisions, outs=None, stream=None):
     with _on_device(dev):
         st = _lib.lib().boys_eval_batched(arr, len(xs), _stream_ptr(stream, dev))
     _lib.check(st, "boys_eval_batched")
+    return outs
+
+
+def boys_eval_batched_noalloc(xs, n_maxs, precisions, outs=None, stream=None):
+    """boys_eval_batched without device allocations inside the library (its tables go to
+    a fixed device array); the call returns after the batch has finished.  Outputs the
+    caller does not pass are allocated here, by torch, before the call."""
+    torch = _torch()
+    arr, outs = _arrays(xs, n_maxs, precisions, outs)
+    dev = xs[0].device if xs else torch.device("cuda")
+    with _on_device(dev):
+        st = _lib.lib().boys_eval_batched_noalloc(arr, len(xs), _stream_ptr(stream, dev))
+    _lib.check(st, "boys_eval_batched_noalloc")
     return outs
 
 

@@ -22,6 +22,7 @@ ERR_INVALID_ARGUMENT = 1
 ERR_UNSUPPORTED_NMAX = 2
 ERR_OUT_OF_MEMORY = 3
 ERR_DEVICE = 4
+ERR_TOO_LARGE = 5
 
 # every function declared in include/boys.h
 EXPORTS = (
@@ -30,6 +31,7 @@ EXPORTS = (
     "boys_eval_split",
     "boys_eri_ssss",
     "boys_eval_batched",
+    "boys_eval_batched_noalloc",
     "boys_plan_create",
     "boys_plan_update",
     "boys_plan_execute",
@@ -110,6 +112,8 @@ def lib():
         L.boys_eri_ssss.restype = ctypes.c_int
         L.boys_eval_batched.argtypes = [ctypes.POINTER(BoysArray), i32, vp]
         L.boys_eval_batched.restype = ctypes.c_int
+        L.boys_eval_batched_noalloc.argtypes = [ctypes.POINTER(BoysArray), i32, vp]
+        L.boys_eval_batched_noalloc.restype = ctypes.c_int
         L.boys_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(BoysArray), i32,
                                        ctypes.POINTER(BoysTuning)]
         L.boys_plan_create.restype = ctypes.c_int

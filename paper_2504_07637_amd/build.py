@@ -6,7 +6,8 @@ Steps: regenerate csrc/boys_tables.inc from data/boys_coeffs.txt; compile, in pa
 the host side (csrc/boys_lib.hip), the serving loop (csrc/boys_serve.hip), the plain
 kernels once per precision class (csrc/plain_inst.hip) and the batched kernels once per
 (n_max bucket, launch shape) (csrc/batched_inst.hip), the two-approximation kernels
-(csrc/split_inst.hip) and the consumer kernels (csrc/eri_inst.hip) into objects under
+(csrc/split_inst.hip), the consumer kernels (csrc/eri_inst.hip) and the allocation-free
+batched entry point (csrc/boys_noalloc.hip) into objects under
 _build/; link them into paper_2504_07637_amd/libboys.so.  BOYS_BUILD_JOBS caps the parallel compiles
 (default: the CPU count, at most 16).
 """
@@ -70,7 +71,8 @@ def _units():
              for sc, k in sorted(SHAPES, key=lambda t: -t[1])]
     units += [(f"plain_c{c}", "plain_inst.hip", [f"-DBOYS_CLASS={c}"]) for c in CLASSES]
     units += [("split", "split_inst.hip", []), ("eri", "eri_inst.hip", [])]
-    units += [("boys_lib", "boys_lib.hip", []), ("boys_serve", "boys_serve.hip", [])]
+    units += [("boys_lib", "boys_lib.hip", []), ("boys_serve", "boys_serve.hip", []),
+              ("boys_noalloc", "boys_noalloc.hip", [])]
     return units
 
 

@@ -678,6 +678,8 @@ const char *boys_status_string(boys_status status)
         return "out of device memory";
     case BOYS_ERR_DEVICE:
         return "device error";
+    case BOYS_ERR_TOO_LARGE:
+        return "batch too large for the fixed scratch array";
     }
     return "unknown status";
 }

@@ -129,3 +129,35 @@ def test_queries():
     assert lib.boys_cutoff(99, L.FP64) != lib.boys_cutoff(99, L.FP64)  # NaN
     for s in range(5):
         assert lib.boys_status_string(s)
+
+
+def test_noalloc_batch_is_checked_on_the_host():
+    # boys_eval_batched_noalloc rejects bad arrays and batches whose tables exceed its fixed
+    # scratch array before it touches a device
+    L = _lib()
+    lib = L.lib()
+    fake = 0x1000  # never dereferenced: every call below fails before any enqueue
+    assert lib.boys_eval_batched_noalloc(None, -1, None) == L.ERR_INVALID_ARGUMENT
+    assert lib.boys_eval_batched_noalloc(None, 1, None) == L.ERR_INVALID_ARGUMENT
+    arr = (L.BoysArray * 2)()
+    for a in arr:
+        a.x, a.out, a.n, a.ld_out, a.n_max, a.precision = fake, fake, 10, 10, 4, L.FP64
+    arr[1].n_max = lib.boys_max_nmax(L.FP64) + 1
+    assert lib.boys_eval_batched_noalloc(arr, 2, None) == L.ERR_UNSUPPORTED_NMAX
+    arr[1].n_max, arr[1].ld_out = 4, 9
+    assert lib.boys_eval_batched_noalloc(arr, 2, None) == L.ERR_INVALID_ARGUMENT
+    arr[1].ld_out, arr[1].precision = 10, 9
+    assert lib.boys_eval_batched_noalloc(arr, 2, None) == L.ERR_INVALID_ARGUMENT
+    # 2^30 arguments: 4 Mi tiles of 8 bytes, more than the 8 MiB array holds
+    arr[1].precision, arr[1].n, arr[1].ld_out = L.FP64, 1 << 30, 1 << 30
+    assert lib.boys_eval_batched_noalloc(arr, 2, None) == L.ERR_TOO_LARGE
+    # the largest that fits: (8 MiB - 512) / 8 tiles beside two descriptors
+    arr[1].n = ((8 << 20) - 512) // 8 * 256 - 1
+    arr[1].ld_out = arr[1].n
+    arr[0].n = arr[0].ld_out = 256  # one more tile than fits
+    assert lib.boys_eval_batched_noalloc(arr, 2, None) == L.ERR_TOO_LARGE
+    # too many descriptors, even with no arguments at all (zeroed entries: empty
+    # binary64 arrays of order 0)
+    many = (L.BoysArray * 210000)()
+    assert lib.boys_eval_batched_noalloc(many, 210000, None) == L.ERR_TOO_LARGE
+    assert lib.boys_status_string(L.ERR_TOO_LARGE) == b"batch too large for the fixed scratch array"
