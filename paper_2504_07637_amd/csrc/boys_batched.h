@@ -16,20 +16,35 @@
 
 namespace {
 
-// one argument of class C (a boys_precision value) at order N
+// one argument of class C (a boys_precision value) at order N, its x already loaded: the
+// tile functions below load a tile's arguments before any of its stores.  Every wait for
+// a vector load here is a wait for all of the wave's outstanding vector memory operations
+// (loads and stores share one counter), so a load issued after stores would hold the
+// wave until those stores have drained.
 template <int C, int N>
-__device__ __forceinline__ void body(const Desc &d, int64_t i, const double2 *tab)
+__device__ __forceinline__ void body_x(const Desc &d, int64_t i, double xi, const double2 *tab)
 {
-    if constexpr (C == BOYS_FP64)
-        body_f64<N>(d.x, static_cast<double *>(d.out), d.ld, i, tab);
-    else if constexpr (C == BOYS_FP64_PLUS)
-        body_f64plus<N>(d.x, static_cast<double *>(d.out), d.ld, i, tab);
-    else if constexpr (C == BOYS_FP32X)
-        body_f32x<N>(d.x, static_cast<float *>(d.out), d.ld, i, tab);
-    else if constexpr (C == BOYS_FP32_SINGLE)
-        body_f32s<N>(d.x, static_cast<float *>(d.out), d.ld, i, tab);
-    else
-        body_f32<N>(d.x, static_cast<float *>(d.out), d.ld, i, tab);
+    if constexpr (C == BOYS_FP64) {
+        double F[N + 1];
+        boys::eval_f64<N>(xi, tab, F);
+        store_rows<N>(F, static_cast<double *>(d.out) + i, d.ld);
+    } else if constexpr (C == BOYS_FP64_PLUS) {
+        double F[N + 2];
+        boys::eval_f64<N + 1>(xi, tab, F);
+        store_rows<N>(F, static_cast<double *>(d.out) + i, d.ld);
+    } else if constexpr (C == BOYS_FP32X) {
+        double F[N + 1];
+        boys::eval_f32r<N>(xi, tab, F);
+        store_rows_f32<N>(F, static_cast<float *>(d.out) + i, d.ld);
+    } else if constexpr (C == BOYS_FP32_SINGLE) {
+        float F[N + 1];
+        boys::eval_f32s<N>(xi, tab, F);
+        store_rows<N>(F, static_cast<float *>(d.out) + i, d.ld);
+    } else {
+        float F[N + 1];
+        boys::eval_f32<N>(xi, tab, F);
+        store_rows<N>(F, static_cast<float *>(d.out) + i, d.ld);
+    }
 }
 
 // The batched kernels inline all 4 x 37 (class, order) bodies, times the unroll factor K.
@@ -38,47 +53,53 @@ __device__ __forceinline__ void body(const Desc &d, int64_t i, const double2 *ta
 // so they stay inlined and the build compiles each (bucket, K) kernel in a unit of its
 // own, in parallel.
 
-// the exp table as the bodies of class C read it: binary64 classes from global memory
-// through L1, the mixed class from the LDS copy that the kernel stages in s_exp_tab
+// The exp table, staged in LDS by every batched kernel, for every class: a table read
+// through L1 is a vector load, and its wait would also wait for the rows that the
+// previous argument of the tile has stored (see body_x); an LDS read has a counter of its
+// own.
 __shared__ double2 s_exp_tab[256];
 
-template <int C>
-__device__ __forceinline__ const double2 *exp_tab()
-{
-    if constexpr (C == BOYS_FP32)
-        return s_exp_tab;
-    else
-        return reinterpret_cast<const double2 *>(boys_tab::kExp2Tab);
-}
-
-// arguments [start, start + cnt) of one array, blockDim-strided
+// arguments [start, start + cnt) of one array, blockDim-strided; each thread loads its
+// next argument before it stores the current one's rows
 template <int C, int N>
 __device__ __forceinline__ void tile_strided(const double *x, void *out, int64_t ld, int64_t start,
                                           int64_t cnt)
 {
     const Desc d{x, out, start + cnt, ld, N, C};
-    const double2 *tab = exp_tab<C>();
-    for (int64_t j = threadIdx.x; j < cnt; j += blockDim.x)
-        body<C, N>(d, start + j, tab);
+    const double2 *tab = s_exp_tab;
+    int64_t j = threadIdx.x;
+    double xn = j < cnt ? load_nt(x + start + j) : 0.0;
+    for (; j < cnt; j += blockDim.x) {
+        const double xc = xn;
+        if (j + blockDim.x < cnt)
+            xn = load_nt(x + start + j + blockDim.x);
+        body_x<C, N>(d, start + j, xc, tab);
+    }
 }
 
-// K guarded iterations, fully unrolled (no loop): a tile of K * blockDim arguments
-// (Wave: a tile of K * 64 arguments owned by one wave, the exp table read through L1 for
-// every class, so that the waves of a workgroup need no barrier)
+// K guarded iterations, fully unrolled (no loop): a tile of K * blockDim arguments, all K
+// arguments loaded first (Wave: a tile of K * 64 arguments owned by one wave)
 template <int C, int N, int K, bool Wave>
 __device__ __forceinline__ void tile_unrolled(const double *x, void *out, int64_t n, int64_t ld,
                                            int64_t start)
 {
     const Desc d{x, out, n, ld, N, C};
-    const double2 *tab =
-        Wave ? reinterpret_cast<const double2 *>(boys_tab::kExp2Tab) : exp_tab<C>();
+    const double2 *tab = s_exp_tab;
     const int stride = Wave ? 64 : (int)blockDim.x;
     const int lane = Wave ? (int)(threadIdx.x & 63u) : (int)threadIdx.x;
+    // unconditional loads (a lane past the end reads the array's last argument): the wait
+    // for each argument then counts only the operations issued after it
+    double xv[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        const int64_t i = start + (int64_t)a * stride + lane;
+        xv[a] = load_nt(x + (i < n ? i : n - 1));
+    }
 #pragma unroll
     for (int a = 0; a < K; ++a) {
         const int64_t i = start + (int64_t)a * stride + lane;
         if (i < n)
-            body<C, N>(d, i, tab);
+            body_x<C, N>(d, i, xv[a], tab);
     }
 }
 
@@ -142,9 +163,8 @@ __global__ __launch_bounds__(256) void k_batched(const Desc *__restrict__ descs,
     }
 }
 
-// one workgroup per tile: the hardware dispatcher hands out the tiles in table order
-// (longest first), no work counter; binary64 bodies read the exp table through L1,
-// binary32 bodies stage it in LDS, as the plain kernels do
+// one workgroup per tile: the hardware dispatcher hands out the tiles in table order, no
+// work counter
 template <int MAXN, int K>
 __global__ __launch_bounds__(256) void k_batched_wg(const Desc *__restrict__ descs,
                                                     const int2 *__restrict__ tiles,
@@ -155,8 +175,7 @@ __global__ __launch_bounds__(256) void k_batched_wg(const Desc *__restrict__ des
     const Desc d = descs[a];
     const int64_t start = (int64_t)__builtin_amdgcn_readfirstlane(ts.y) * tile_args;
     const int prec = __builtin_amdgcn_readfirstlane(d.prec);
-    if (prec == BOYS_FP32)
-        load_exp_table(s_exp_tab);
+    load_exp_table(s_exp_tab);
     dispatch_class<MAXN, 1, K>(prec, __builtin_amdgcn_readfirstlane(d.n_max), d, start, 0);
 }
 
@@ -167,6 +186,8 @@ __global__ __launch_bounds__(256) void k_batched_wave(const Desc *__restrict__ d
                                                       const int2 *__restrict__ tiles,
                                                       int32_t ntiles, int32_t tile_args)
 {
+    // every thread reaches the barrier in load_exp_table before any leaves
+    load_exp_table(s_exp_tab);
     const int32_t w = __builtin_amdgcn_readfirstlane(
         (int32_t)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
     if (w >= ntiles)

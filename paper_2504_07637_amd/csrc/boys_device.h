@@ -309,6 +309,12 @@ __host__ __device__ __forceinline__ T factors(T x, const T (&g)[NG > 0 ? NG : 1]
 // ---------------------------------------------------------------------------------
 // F_0..F_N for one argument, binary64 class
 
+// The two sides of the cut-off share one division and one square root, at the same place
+// in the code: below it u/v and c_n / (G^n sqrt(G)), past it 1/x and c_0 / (1 sqrt(x)).  Each
+// lane performs exactly the correctly rounded operations of its own side on the operands
+// that side selects (a product with 1 is exact), so the values are those of two separate
+// branches bit for bit; a wave with lanes on both sides (on the integral workload nearly
+// every wave) issues the division and the square root once instead of once per side.
 template <class S, int N, bool RcpRecursion = false>
 __host__ __device__ __forceinline__ void eval_f64_set(double x, const double2 *__restrict__ tab,
                                                       double (&F)[N + 1])
@@ -316,29 +322,38 @@ __host__ __device__ __forceinline__ void eval_f64_set(double x, const double2 *_
     // outside the domain (x < 0) the argument becomes NaN, which every step below carries
     // into every row (fmax keeps the exponential's argument finite)
     x = x >= 0.0 ? x : __builtin_nan("");
-    if (!(x > S::z)) {
-        // below the cut-off, and NaN
-        const double e = exp_rn(__builtin_fmax(-x, -120.0), tab);
-        const double u = factors<double, S::ug_n, S::uq_n, S::ul_n>(x, S::ug, S::uq, S::ul);
-        const double v = factors<double, S::vg_n, S::vq_n, S::vl_n>(x, S::vg, S::vq, S::vl);
-        const double Q = S::q0 + S::q1 * x + S::q2 * (u / v) * x * x;
+    const bool below = !(x > S::z);  // below the cut-off, and NaN
+    double e = 0.0, num = 1.0, den = x;
+    if (below) {
+        e = exp_rn(__builtin_fmax(-x, -120.0), tab);
+        num = factors<double, S::ug_n, S::uq_n, S::ul_n>(x, S::ug, S::uq, S::ul);
+        den = factors<double, S::vg_n, S::vq_n, S::vl_n>(x, S::vg, S::vq, S::vl);
+    }
+    const double d = num / den;  // u/v below the cut-off, 1/x past it
+    double C = boys_tab::kC0, G = x, Gn = 1.0;
+    if (below) {
+        const double Q = S::q0 + S::q1 * x + S::q2 * d * x * x;
         const double W = powi<N>(Q) * __builtin_sqrt(Q) * e;
-        const double G = x + W;
-        const double f = S::c / (powi<N>(G) * __builtin_sqrt(G));
+        G = x + W;
+        Gn = powi<N>(G);
+        C = S::c;
+    }
+    // F_n below the cut-off; past it F_0 of Eq. limf1 (x = +inf gives 0 everywhere)
+    const double f = C / (Gn * __builtin_sqrt(G));
+    if (below) {
         F[N] = f;
         if constexpr (RcpRecursion)
             recurse_down_rcp<N, double>(2.0 * x, e, f, F);
         else
             recurse_down<N, double>(2.0 * x, e, f, F);
     } else {
-        // Eq. limf1 for every m; x = +inf gives 0 everywhere
-        const double ix = 1.0 / x;
-        double f = boys_tab::kC0 / __builtin_sqrt(x);
-        F[0] = f;
+        // Eq. limf1 for every m, generated upward with d = 1/x
+        double g = f;
+        F[0] = g;
 #pragma unroll
         for (int m = 1; m <= N; ++m) {
-            f = f * (m - 0.5) * ix;
-            F[m] = f;
+            g = g * (m - 0.5) * d;
+            F[m] = g;
         }
     }
 }
@@ -486,6 +501,9 @@ __host__ __device__ __forceinline__ void eval_split(double x, int nbar,
 // ---------------------------------------------------------------------------------
 // F_0..F_N for one argument, mixed binary32/binary64 class
 
+// Separate branches here: sharing the binary64 division and square root between the two
+// sides, as eval_f64_set does, measured 3.6% slower for this class's full-row kernel
+// (0.897 against 0.866 ms at n_max = 16, 2^26 arguments), though fewer instructions.
 template <int N>
 __host__ __device__ __forceinline__ void eval_f32(double x, const double2 *__restrict__ tab,
                                                   float (&F)[N + 1])

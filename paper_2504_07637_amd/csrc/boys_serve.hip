@@ -5,7 +5,7 @@
 //     contiguous piece of it: its x copy, then its (n_max+1) output rows, each starting
 //     on a 128-byte boundary (ld = n rounded up to 16 binary64 / 32 binary32 elements);
 //   * K execution slots, each a HIP stream with its own pinned staging and device
-//     buffers for the descriptor and tile tables and its own work counter;
+//     buffers for the descriptor and tile tables;
 //   * a launch on a slot enqueues, in stream order, the host-to-device copies of the
 //     batch's arguments and tables, then the batched kernel with one workgroup per tile
 //     (the same per-argument bodies as boys_eval), then an event; the slot is free again
@@ -50,7 +50,6 @@ struct HipExec {
     std::vector<int2 *> h_tiles;
     std::vector<Desc *> d_desc;
     std::vector<int2 *> d_tiles;
-    std::vector<uint32_t *> d_counter;
     std::vector<hipEvent_t> read_events;       // every read event created
     std::vector<hipEvent_t> read_events_free;  // those not in use
     std::atomic<uint64_t> errors{0};
@@ -144,7 +143,7 @@ struct HipExec {
                                   hipMemcpyHostToDevice, st) == hipSuccess;
         const boys_internal::Launch L{schedule, (int)tile, block, grid};
         ok = ok && boys_internal::launch_batched(d_desc[s], d_tiles[s], (int32_t)ts.size(),
-                                                 d_counter[s], maxn, L, st) == hipSuccess;
+                                                 nullptr, maxn, L, st) == hipSuccess;
         ok = ok && hipEventRecord(events[s], st) == hipSuccess;
         if (!ok) {
             // wait for whatever part of the batch was enqueued (copies from the slot's
@@ -217,8 +216,6 @@ void destroy_exec(HipExec &ex)
             (void)hipFree(ex.d_desc[i]);
         if (ex.d_tiles[i])
             (void)hipFree(ex.d_tiles[i]);
-        if (ex.d_counter[i])
-            (void)hipFree(ex.d_counter[i]);
     }
     if (ex.pool_base)
         (void)hipFree(ex.pool_base);
@@ -258,7 +255,6 @@ boys_status boys_server_create(boys_server **out, const boys_server_config *cfg)
     ex.h_tiles.assign(streams, nullptr);
     ex.d_desc.assign(streams, nullptr);
     ex.d_tiles.assign(streams, nullptr);
-    ex.d_counter.assign(streams, nullptr);
     bool ok = hipMalloc(&ex.pool_base, (size_t)cfg->budget_bytes) == hipSuccess;
     boys_status st = ok ? BOYS_OK : BOYS_ERR_OUT_OF_MEMORY;
     for (int i = 0; i < streams && ok; ++i) {
@@ -269,8 +265,7 @@ boys_status boys_server_create(boys_server **out, const boys_server_config *cfg)
              hipHostMalloc((void **)&ex.h_tiles[i], sizeof(int2) * max_tiles, hipHostMallocDefault) ==
                  hipSuccess &&
              hipMalloc(&ex.d_desc[i], sizeof(Desc) * max_batch) == hipSuccess &&
-             hipMalloc(&ex.d_tiles[i], sizeof(int2) * max_tiles) == hipSuccess &&
-             hipMalloc(&ex.d_counter[i], 256) == hipSuccess;
+             hipMalloc(&ex.d_tiles[i], sizeof(int2) * max_tiles) == hipSuccess;
         if (!ok)
             st = BOYS_ERR_OUT_OF_MEMORY;
     }
