@@ -168,8 +168,9 @@ typedef struct {
 
 /*
  * Launch parameters of a batched launch (0 in tile/block/grid_per_cu = library default).
- * schedule 0: persistent workgroups (grid_per_cu per compute unit) take tiles from a work
- *             counter in table order;
+ * schedule 0: persistent waves: grid_per_cu resident workgroups per compute unit (at
+ *             least 8 in all) whose waves each take 256-argument tiles (tile must be 256)
+ *             from one of 8 work counters, the tile list dealt round-robin to the 8;
  * schedule 1: one workgroup per tile, dispatched by the hardware in table order;
  *             tile must be block x 1, 2 or 4.
  * schedule 2: one wave per tile (tile = 256, i.e. 64 lanes x 4 arguments; a block of
@@ -181,7 +182,7 @@ typedef struct {
  *             both launches.
  */
 typedef struct {
-    int32_t tile;        /* arguments per tile, a multiple of the block size */
+    int32_t tile;        /* arguments per tile: schedule 1 block x 1, 2 or 4; 0 and 2: 256 */
     int32_t block;       /* threads per workgroup: 64, 128 or 256 */
     int32_t grid_per_cu; /* schedule 0: persistent workgroups per compute unit (1..64) */
     int32_t schedule;    /* 0, 1 or 2 (above) */
@@ -225,7 +226,7 @@ boys_status boys_eval_batched_noalloc(const boys_array *arrays, int32_t count, v
  * [reset counter, persistent kernel]; schedule 1: [one workgroup per tile]; schedule 2:
  * [one wave per tile], after [one workgroup per tile] for the store-bound arrays of a
  * split plan) built once for a batch and replayed by boys_plan_execute.  tuning may be
- * NULL for the defaults: schedule 2, tile 256, block 256, order 1, split_nmax 12.
+ * NULL for the defaults: schedule 2, tile 256, block 256, order 1, split_nmax 0.
  * boys_eval_batched uses the defaults.  boys_plan_update replaces the x/out pointers of a
  * batch with the same count, lengths, n_max and precisions (other changes return
  * BOYS_ERR_INVALID_ARGUMENT); it first waits for every execute of the plan already

@@ -297,9 +297,8 @@ def _tuning(t):
 class Plan:
     """A batched schedule captured in a HIP graph; execute() replays it.
 
-    tuning: None for the library defaults (one wave per tile, with the store-bound arrays
-    in a launch of their own), or a dict of boys_tuning fields (tile, block, grid_per_cu,
-    schedule, order, split_nmax)."""
+    tuning: None for the library defaults (one wave per 256-argument tile, one launch), or a
+    dict of boys_tuning fields (tile, block, grid_per_cu, schedule, order, split_nmax)."""
 
     def __init__(self, xs, n_maxs, precisions, outs=None, tuning=None):
         torch = _torch()

@@ -1,6 +1,6 @@
 // batched_inst.hip -- one batched kernel and its launcher: n_max bucket B (the largest
-// order it dispatches is kBuckets[B]), schedule S (0: persistent workgroups with a work
-// counter; 1: one workgroup per tile of K * blockDim arguments, K = 1, 2, 4; 2: one wave
+// order it dispatches is kBuckets[B]), schedule S (0: persistent waves with work
+// counters; 1: one workgroup per tile of K * blockDim arguments, K = 1, 2, 4; 2: one wave
 // per tile of K * 64 arguments, K = 4).
 // Compiled once per (B, S, K) with -DBOYS_BUCKET=<B> -DBOYS_SCHED=<S> -DBOYS_K=<K>.
 #include <algorithm>
@@ -25,9 +25,10 @@ hipError_t boys_internal::launch_bucket(const Desc *d_desc, const int2 *d_tiles,
                                dim3(L.block), 0, s, d_desc, d_tiles, ntiles, L.tile);
     } else if constexpr (S == 0) {
         hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, d_counter);
+        // at least 8 workgroups: one per work queue
         if (ntiles > 0)
-            hipLaunchKernelGGL((k_batched<kMax>), dim3(std::max(1, std::min(L.grid, ntiles))),
-                               dim3(L.block), 0, s, d_desc, d_tiles, ntiles, L.tile, d_counter);
+            hipLaunchKernelGGL((k_batched<kMax>), dim3(std::max(8, L.grid)), dim3(L.block), 0, s,
+                               d_desc, d_tiles, ntiles, d_counter);
     } else {
         static_assert(K == 1 || K == 2 || K == 4, "unsupported tile factor");
         if (ntiles > 0)

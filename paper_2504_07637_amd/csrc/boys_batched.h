@@ -1,14 +1,15 @@
 // boys_batched.h -- the batched kernels (included by batched_inst.hip, one n_max bucket and
 // one launch shape per unit).
 //
-//   k_batched<MAXN>  persistent workgroups pull tiles from a device counter; a tile is
-//                    one slice of one array, so (precision, n_max) is uniform per tile and
-//                    the per-tile dispatch is a scalar branch to the same unrolled bodies
-//                    that k_plain uses, which makes batched results equal to solo ones
-//                    bit for bit.
+//   k_batched<MAXN>  persistent waves: each wave on its own takes 256-argument tiles from
+//                    one of eight work counters and loads the next tile's arguments before
+//                    it stores the current one's rows; a tile is one slice of one array, so
+//                    (precision, n_max) is uniform per tile and the per-tile dispatch is a
+//                    scalar branch to the same unrolled bodies that k_plain uses, which
+//                    makes batched results equal to solo ones bit for bit.
 //   k_batched_wg<MAXN, K>  one workgroup per tile of K * blockDim arguments.
 //   k_batched_wave<MAXN, K>  one wave per tile of K * 64 arguments.
-//   k_reset          zeroes the tile counter (a kernel rather than a memset node, so the
+//   k_reset          zeroes the work counters (a kernel rather than a memset node, so the
 //                    plan's graph replays correctly).
 #pragma once
 
@@ -59,21 +60,29 @@ __device__ __forceinline__ void body_x(const Desc &d, int64_t i, double xi, cons
 // own.
 __shared__ double2 s_exp_tab[256];
 
-// arguments [start, start + cnt) of one array, blockDim-strided; each thread loads its
-// next argument before it stores the current one's rows
+// One 256-argument tile of the persistent schedule (4 arguments per lane, their values xv
+// loaded by the caller).  Before it stores anything, it loads the next tile's arguments
+// into xn (nx: the next tile's first argument, nn >= 1 arguments from there on; nx null:
+// no next tile), so that waiting for them later does not wait for these stores.
 template <int C, int N>
-__device__ __forceinline__ void tile_strided(const double *x, void *out, int64_t ld, int64_t start,
-                                          int64_t cnt)
+__device__ __forceinline__ void tile_persistent(const Desc &d, int64_t start,
+                                                const double (&xv)[4], const double *nx,
+                                                int64_t nn, double (&xn)[4])
 {
-    const Desc d{x, out, start + cnt, ld, N, C};
-    const double2 *tab = s_exp_tab;
-    int64_t j = threadIdx.x;
-    double xn = j < cnt ? load_nt(x + start + j) : 0.0;
-    for (; j < cnt; j += blockDim.x) {
-        const double xc = xn;
-        if (j + blockDim.x < cnt)
-            xn = load_nt(x + start + j + blockDim.x);
-        body_x<C, N>(d, start + j, xc, tab);
+    const int lane = (int)(threadIdx.x & 63u);
+    if (nx != nullptr) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int64_t i = (int64_t)a * 64 + lane;
+            xn[a] = load_nt(nx + (i < nn ? i : nn - 1));
+        }
+    }
+    const Desc e{d.x, d.out, d.n, d.ld, N, C};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int64_t i = start + (int64_t)a * 64 + lane;
+        if (i < d.n)
+            body_x<C, N>(e, i, xv[a], s_exp_tab);
     }
 }
 
@@ -104,18 +113,46 @@ __device__ __forceinline__ void tile_unrolled(const double *x, void *out, int64_
 }
 
 // scalar dispatch over n (wave-uniform) to the tile functions of orders N, N-1, ..., 0;
-// S: 0 the strided form (persistent schedule), 1 one workgroup per tile, 2 one wave per tile
+// S: 1 one workgroup per tile, 2 one wave per tile
 template <int C, int N, int S, int K>
 __device__ __forceinline__ void dispatch(int n, const Desc &d, int64_t start, int64_t cnt)
 {
-    if (n == N) {
-        if constexpr (S == 0)
-            tile_strided<C, N>(d.x, d.out, d.ld, start, cnt);
-        else
-            tile_unrolled<C, N, K, S == 2>(d.x, d.out, d.n, d.ld, start);
-    } else if constexpr (N > 0) {
+    if (n == N)
+        tile_unrolled<C, N, K, S == 2>(d.x, d.out, d.n, d.ld, start);
+    else if constexpr (N > 0)
         dispatch<C, N - 1, S, K>(n, d, start, cnt);
-    }
+}
+
+// the same dispatch for the persistent schedule's tiles
+template <int C, int N>
+__device__ __forceinline__ void dispatch_p(int n, const Desc &d, int64_t start,
+                                           const double (&xv)[4], const double *nx, int64_t nn,
+                                           double (&xn)[4])
+{
+    if (n == N)
+        tile_persistent<C, N>(d, start, xv, nx, nn, xn);
+    else if constexpr (N > 0)
+        dispatch_p<C, N - 1>(n, d, start, xv, nx, nn, xn);
+}
+
+template <int MAXN>
+__device__ __forceinline__ void dispatch_class_p(int prec, int n, const Desc &d, int64_t start,
+                                                 const double (&xv)[4], const double *nx,
+                                                 int64_t nn, double (&xn)[4])
+{
+    if (prec == BOYS_FP64)
+        dispatch_p<BOYS_FP64, cmin(MAXN, class_max<BOYS_FP64>())>(n, d, start, xv, nx, nn, xn);
+    else if (prec == BOYS_FP32)
+        dispatch_p<BOYS_FP32, cmin(MAXN, class_max<BOYS_FP32>())>(n, d, start, xv, nx, nn, xn);
+    else if (prec == BOYS_FP32X)
+        dispatch_p<BOYS_FP32X, cmin(MAXN, class_max<BOYS_FP32X>())>(n, d, start, xv, nx, nn,
+                                                                    xn);
+    else if (prec == BOYS_FP32_SINGLE)
+        dispatch_p<BOYS_FP32_SINGLE, cmin(MAXN, class_max<BOYS_FP32_SINGLE>())>(n, d, start, xv,
+                                                                                nx, nn, xn);
+    else
+        dispatch_p<BOYS_FP64_PLUS, cmin(MAXN, class_max<BOYS_FP64_PLUS>())>(n, d, start, xv, nx,
+                                                                            nn, xn);
 }
 
 template <int MAXN, int S, int K>
@@ -136,30 +173,77 @@ __device__ __forceinline__ void dispatch_class(int prec, int n, const Desc &d, i
                                                                                  cnt);
 }
 
+// Persistent waves (schedule 0): a grid of resident workgroups whose waves work on their
+// own, with no barrier after the exp table is staged.  The tile list is dealt to 8 queues,
+// queue q holding tiles q, q + 8, q + 16, ... (an even share of every part of the list);
+// workgroup b serves queue b mod 8 (the dispatcher places workgroup b on XCD b mod 8, so
+// the waves of one XCD share a counter), and its waves take kPersistentChunk tiles at a
+// time from that queue's counter until the queue is empty.  Every queue q < ntiles needs
+// a workgroup with b mod 8 = q: the host launches at least 8.
+__device__ __forceinline__ int32_t grab(uint32_t *ctr)
+{
+    uint32_t k = 0;
+    if ((threadIdx.x & 63u) == 0)
+        k = atomicAdd(ctr, (uint32_t)boys_internal::kPersistentChunk);
+    // every lane is active again here, so the first active lane is lane 0
+    return (int32_t)__builtin_amdgcn_readfirstlane(k);
+}
+
 template <int MAXN>
 __global__ __launch_bounds__(256) void k_batched(const Desc *__restrict__ descs,
                                                  const int2 *__restrict__ tiles,
-                                                 int32_t ntiles, int32_t tile_args,
-                                                 uint32_t *__restrict__ counter)
+                                                 int32_t ntiles, uint32_t *__restrict__ counters)
 {
-    __shared__ int32_t s_tile;
-    load_exp_table(s_exp_tab);
+    using boys_internal::kPersistentChunk;
+    load_exp_table(s_exp_tab);  // every thread reaches its barrier before any leaves
+    const int32_t q = (int32_t)(blockIdx.x & 7u);
+    if (q >= ntiles)
+        return;
+    const int32_t nq = (ntiles - q + 7) / 8;  // tiles in queue q
+    uint32_t *ctr = counters + boys_internal::kCounterStride * q;
+    const int lane = (int)(threadIdx.x & 63u);
+    int32_t k = grab(ctr);
+    if (k >= nq)
+        return;
+    int32_t kend = k + kPersistentChunk < nq ? k + kPersistentChunk : nq;
+    int2 ts = tiles[q + 8 * k];
+    Desc d = descs[__builtin_amdgcn_readfirstlane(ts.x)];
+    int64_t start = (int64_t)__builtin_amdgcn_readfirstlane(ts.y) * 256;
+    double xv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int64_t i = start + (int64_t)a * 64 + lane;
+        xv[a] = load_nt(d.x + (i < d.n ? i : d.n - 1));
+    }
     for (;;) {
-        if (threadIdx.x == 0)
-            s_tile = (int32_t)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int32_t t = __builtin_amdgcn_readfirstlane(s_tile);
-        __syncthreads();
-        if (t >= ntiles)
+        int32_t kn = k + 1;
+        if (kn >= kend) {
+            kn = grab(ctr);
+            kend = kn + kPersistentChunk < nq ? kn + kPersistentChunk : nq;
+        }
+        Desc dn{};
+        int64_t sn = 0;
+        const double *nx = nullptr;
+        int64_t nn = 0;
+        if (kn < nq) {
+            ts = tiles[q + 8 * kn];
+            dn = descs[__builtin_amdgcn_readfirstlane(ts.x)];
+            sn = (int64_t)__builtin_amdgcn_readfirstlane(ts.y) * 256;
+            nx = dn.x + sn;
+            nn = dn.n - sn;
+        }
+        double xn[4] = {0.0, 0.0, 0.0, 0.0};
+        dispatch_class_p<MAXN>(__builtin_amdgcn_readfirstlane(d.prec),
+                               __builtin_amdgcn_readfirstlane(d.n_max), d, start, xv, nx, nn, xn);
+        if (nx == nullptr)
             break;
-        const int2 ts = tiles[t];
-        const int32_t a = __builtin_amdgcn_readfirstlane(ts.x);
-        const Desc d = descs[a];
-        const int64_t start = (int64_t)__builtin_amdgcn_readfirstlane(ts.y) * tile_args;
-        const int64_t rem = d.n - start;
-        const int64_t cnt = rem < tile_args ? rem : tile_args;
-        dispatch_class<MAXN, 0, 0>(__builtin_amdgcn_readfirstlane(d.prec),
-                                __builtin_amdgcn_readfirstlane(d.n_max), d, start, cnt);
+        d = dn;
+        start = sn;
+        xv[0] = xn[0];
+        xv[1] = xn[1];
+        xv[2] = xn[2];
+        xv[3] = xn[3];
+        k = kn;
     }
 }
 
@@ -200,10 +284,11 @@ __global__ __launch_bounds__(256) void k_batched_wave(const Desc *__restrict__ d
                                __builtin_amdgcn_readfirstlane(d.n_max), d, start, 0);
 }
 
-__global__ void k_reset(uint32_t *counter)
+// one wave: zero the 8 work counters of k_batched
+__global__ void k_reset(uint32_t *counters)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0)
-        *counter = 0u;
+    if (threadIdx.x < 8)
+        counters[boys_internal::kCounterStride * threadIdx.x] = 0u;
 }
 
 }  // namespace

@@ -20,19 +20,26 @@ struct Desc {
     int32_t prec;
 };
 
+// schedule 0 (persistent waves): 8 work counters, one per 128-byte line, and the tiles a
+// wave takes from its counter at a time
+constexpr int kCounterStride = 32;                     // uint32 elements between counters
+constexpr int kCounterBytes = 8 * kCounterStride * 4;  // 1 KiB
+constexpr int kPersistentChunk = 4;
+
 // how a batch is launched
 struct Launch {
-    int schedule;  // 0: persistent workgroups + work counter; 1: one workgroup per tile;
+    int schedule;  // 0: persistent waves + work counters; 1: one workgroup per tile;
                    // 2: one wave per tile
-    int tile;      // arguments per tile (schedule 1: block x 1, 2 or 4; schedule 2: 256)
+    int tile;      // arguments per tile (schedule 1: block x 1, 2 or 4; schedules 0 and 2: 256)
     int block;     // threads per workgroup (64, 128, 256)
-    int grid;      // schedule 0: number of persistent workgroups
+    int grid;      // schedule 0: number of persistent workgroups (at least 8)
 };
 
-// Enqueue a batch on stream s: schedule 0 = [zero the counter, persistent kernel],
-// schedule 1 = [one workgroup per tile].  tiles holds (array index, slice index) pairs;
-// slice k of array a covers arguments [k * tile, min((k+1) * tile, n_a)).  maxn is the
-// largest n_max in the batch.
+// Enqueue a batch on stream s: schedule 0 = [zero the counters, persistent kernel],
+// schedule 1 = [one workgroup per tile], schedule 2 = [one wave per tile].  tiles holds
+// (array index, slice index) pairs; slice k of array a covers arguments [k * tile,
+// min((k+1) * tile, n_a)).  d_counter: kCounterBytes of device memory (schedule 0 only).
+// maxn is the largest n_max in the batch.
 hipError_t launch_batched(const Desc *d_desc, const int2 *d_tiles, int32_t ntiles,
                           uint32_t *d_counter, int maxn, const Launch &L, hipStream_t s);
 
@@ -57,8 +64,8 @@ SplitLaunch split_launcher(int n);
 hipError_t launch_eri_ssss(const boys_pair_list &bra, const boys_pair_list &ket, int n_max,
                            double *out, int64_t ld, hipStream_t s);
 
-// the batched kernel of n_max bucket B with schedule S (0: persistent, [zero the counter,
-// kernel]; 1: one workgroup per tile of K * L.block arguments, K = 1, 2, 4; 2: one wave
+// the batched kernel of n_max bucket B with schedule S (0: persistent waves, [zero the
+// counters, kernel]; 1: one workgroup per tile of K * L.block arguments, K = 1, 2, 4; 2: one wave
 // per tile of K * 64 arguments, K = 4); defined per (B, S, K) in batched_inst.hip
 template <int B, int S, int K>
 hipError_t launch_bucket(const Desc *d_desc, const int2 *d_tiles, int32_t ntiles,

@@ -199,12 +199,12 @@ namespace {
 constexpr int kDefaultTile = 256;
 constexpr int kDefaultBlock = 256;
 constexpr int kDefaultGridPerCU = 4;
-// with no tuning: one wave per tile, the store-bound arrays (n_max >= 12, binary32 outputs
-// >= 16) in a launch of their own, the measured best for mixed batches; a batch of low
-// orders only, or of high orders only, gets a single launch
+// with no tuning: one wave per 256-argument tile, array by array, in one launch (on the
+// 8,192-array batch within 0.5% of the best shape measured, and 2-3% ahead of putting the
+// store-bound arrays in a launch of their own)
 constexpr int kDefaultSchedule = 2;
 constexpr int kDefaultOrder = 1;
-constexpr int kDefaultSplit = 12;
+constexpr int kDefaultSplit = 0;
 
 boys_tuning resolve(const boys_tuning *t)
 {
@@ -234,7 +234,7 @@ bool tuning_ok(const boys_tuning &t)
     if (t.split_nmax < 0 || t.split_nmax > 64 || (t.split_nmax != 0 && t.schedule != 2))
         return false;
     if (t.schedule == 0)
-        return t.tile % t.block == 0 && t.grid_per_cu >= 1 && t.grid_per_cu <= 64;
+        return t.tile == 256 && t.grid_per_cu >= 1 && t.grid_per_cu <= 64;
     return shape_row(t.schedule, t.tile, t.block) >= 0;  // schedule 1: tile = block x K
 }
 
@@ -499,13 +499,17 @@ boys_status boys_plan_create(boys_plan **plan, const boys_array *arrays, int32_t
         delete p;
         return st;
     }
+    // schedule 0: grid_per_cu resident workgroups per compute unit, no more than one wave
+    // per tile, at least one workgroup per work queue (8)
+    const int64_t waves_per_wg = tn.block / 64;
     p->grid = (int)std::max<int64_t>(
-        1, std::min<int64_t>((int64_t)cu_count() * tn.grid_per_cu, std::max(p->ntiles, 1)));
+        8, std::min<int64_t>((int64_t)cu_count() * tn.grid_per_cu,
+                             (std::max(p->ntiles, 1) + waves_per_wg - 1) / waves_per_wg));
     const size_t desc_bytes = sizeof(Desc) * std::max<int32_t>(count, 1);
     const size_t tile_bytes = sizeof(int2) * std::max<int32_t>(p->ntiles, 1);
     if (hipMalloc(&p->d_desc, desc_bytes) != hipSuccess ||
         hipMalloc(&p->d_tiles, tile_bytes) != hipSuccess ||
-        hipMalloc(&p->d_counter, 256) != hipSuccess) {
+        hipMalloc(&p->d_counter, boys_internal::kCounterBytes) != hipSuccess) {
         (void)hipGetLastError();
         free_plan_buffers(p);
         delete p;

@@ -3,8 +3,8 @@
 //
 // boys_eval_batched builds a temporary plan: its descriptor and tile tables live in
 // device buffers it allocates and frees inside the call.  This entry point runs the same
-// kernels with the same default schedule (one wave per 256-argument tile; the
-// store-bound arrays first, one 256-thread workgroup per tile) on tables placed in a
+// kernels with the same default schedule (one wave per 256-argument tile, array by array,
+// in one launch) on tables placed in a
 // fixed device array of this file, `scratch`, so it calls no hipMalloc or hipFree.
 //
 // Per device, the first call with that device current looks up the array's device
@@ -27,7 +27,6 @@ using boys_internal::Desc;
 
 constexpr size_t kScratchBytes = size_t(8) << 20;  // BOYS_NOALLOC_SCRATCH_BYTES in boys.h
 constexpr int kTile = 256;                         // arguments per tile
-constexpr int kSplit = 12;  // store-bound: n_max >= 12 (binary64 out), >= 16 (binary32 out)
 constexpr size_t kDescOff = 256;
 
 static_assert(BOYS_NOALLOC_SCRATCH_BYTES == kScratchBytes, "boys.h states the scratch size");
@@ -59,16 +58,6 @@ unsigned char *scratch_ptr(int dev)
     return g_ptr[dev];
 }
 
-int out_bytes(int32_t prec)
-{
-    return prec == BOYS_FP32 || prec == BOYS_FP32X || prec == BOYS_FP32_SINGLE ? 4 : 8;
-}
-
-bool store_bound(const boys_array &a)
-{
-    return a.n_max >= kSplit + (out_bytes(a.precision) == 4 ? 4 : 0);
-}
-
 }  // namespace
 
 extern "C" boys_status boys_eval_batched_noalloc(const boys_array *arrays, int32_t count,
@@ -89,17 +78,13 @@ extern "C" boys_status boys_eval_batched_noalloc(const boys_array *arrays, int32
             return BOYS_ERR_INVALID_ARGUMENT;
     }
     // table sizes against the fixed array
-    int64_t ntiles = 0, nhi = 0;
-    int maxn = 0, maxn_hi = 0;
+    int64_t ntiles = 0;
+    int maxn = 0;
     for (int32_t a = 0; a < count; ++a) {
         const int64_t t = (arrays[a].n + kTile - 1) / kTile;
         ntiles += t;
-        if (t > 0 && store_bound(arrays[a])) {
-            nhi += t;
-            maxn_hi = std::max(maxn_hi, (int)arrays[a].n_max);
-        } else if (t > 0) {
+        if (t > 0)
             maxn = std::max(maxn, (int)arrays[a].n_max);
-        }
         if (ntiles > INT32_MAX)
             return BOYS_ERR_TOO_LARGE;
     }
@@ -118,8 +103,8 @@ extern "C" boys_status boys_eval_batched_noalloc(const boys_array *arrays, int32
         return BOYS_ERR_DEVICE;
 
     std::lock_guard<std::mutex> lock(g_mu);
-    // descriptors, then the tiles: the store-bound arrays' tiles first, each array's
-    // tiles consecutive (the order boys_eval_batched's default schedule takes)
+    // descriptors, then the tiles, each array's consecutive (the order of boys_eval_batched's
+    // default schedule)
     Desc *hd = reinterpret_cast<Desc *>(g_host + kDescOff);
     for (int32_t a = 0; a < count; ++a) {
         const boys_array &A = arrays[a];
@@ -127,14 +112,11 @@ extern "C" boys_status boys_eval_batched_noalloc(const boys_array *arrays, int32
     }
     int2 *ht = reinterpret_cast<int2 *>(g_host + tiles_off);
     int64_t k = 0;
-    for (int pass = 0; pass < 2; ++pass)
-        for (int32_t a = 0; a < count; ++a) {
-            if (store_bound(arrays[a]) != (pass == 0))
-                continue;
-            const int64_t t = (arrays[a].n + kTile - 1) / kTile;
-            for (int64_t s = 0; s < t; ++s)
-                ht[k++] = make_int2(a, (int32_t)s);
-        }
+    for (int32_t a = 0; a < count; ++a) {
+        const int64_t t = (arrays[a].n + kTile - 1) / kTile;
+        for (int64_t s = 0; s < t; ++s)
+            ht[k++] = make_int2(a, (int32_t)s);
+    }
     const size_t used = tiles_off + sizeof(int2) * (size_t)ntiles - kDescOff;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const Desc *d_desc = reinterpret_cast<const Desc *>(base + kDescOff);
@@ -142,16 +124,10 @@ extern "C" boys_status boys_eval_batched_noalloc(const boys_array *arrays, int32
     if (hipMemcpyAsync(base + kDescOff, g_host + kDescOff, used, hipMemcpyHostToDevice, s) !=
         hipSuccess)
         return BOYS_ERR_DEVICE;
-    // schedules 1 and 2 use no work counter
+    // schedule 2 uses no work counter
     boys_status st = BOYS_OK;
-    if (nhi > 0 && boys_internal::launch_batched(d_desc, d_tiles, (int32_t)nhi, nullptr, maxn_hi,
-                                                 boys_internal::Launch{1, kTile, 256, 0},
-                                                 s) != hipSuccess)
-        st = BOYS_ERR_DEVICE;
-    if (st == BOYS_OK && ntiles > nhi &&
-        boys_internal::launch_batched(d_desc, d_tiles + nhi, (int32_t)(ntiles - nhi), nullptr,
-                                      maxn, boys_internal::Launch{2, kTile, 256, 0},
-                                      s) != hipSuccess)
+    if (boys_internal::launch_batched(d_desc, d_tiles, (int32_t)ntiles, nullptr, maxn,
+                                      boys_internal::Launch{2, kTile, 256, 0}, s) != hipSuccess)
         st = BOYS_ERR_DEVICE;
     // whatever was enqueued must have read the tables before the next call rewrites them
     if (hipStreamSynchronize(s) != hipSuccess)

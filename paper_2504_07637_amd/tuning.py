@@ -6,12 +6,12 @@ device, library build and a coarse signature of the batch, and keeps it in a JSO
 (``$BOYS_TUNING_FILE``, default ``~/.cache/paper_2504_07637_amd/tuning.json``).
 
 Tunable choices (the per-argument work is one sequential chain, so a lane always owns
-whole arguments): the schedule (persistent workgroups with a work counter, one workgroup
-per tile, or one wave per tile), the workgroup size, the arguments per lane (tile =
-block x 1, 2 or 4 for one workgroup per tile, 64 x 4 for one wave per tile, with the
-store-bound arrays optionally in a launch of their own at one argument per lane), the
-tile order (longest first, array by array, or grouped by class) and, for the persistent
-schedule, the tile size and the number of workgroups per compute unit.
+whole arguments): the schedule (persistent waves with work counters, one workgroup per
+tile, or one wave per tile), the workgroup size, the arguments per lane (tile = block x 1,
+2 or 4 for one workgroup per tile, 64 x 4 for one wave per tile and for the persistent
+waves, with the store-bound arrays optionally in a launch of their own at one argument
+per lane), the tile order (longest first, array by array, or grouped by class) and, for
+the persistent schedule, the number of workgroups per compute unit.
 """
 from __future__ import annotations
 
@@ -25,8 +25,8 @@ from . import _lib
 CANDIDATES = (
     [{"schedule": 1, "block": b, "tile": b * k, "grid_per_cu": 1, "order": o}
      for o in (1, 2, 0) for b in (128, 256) for k in (1, 2, 4)]
-    + [{"schedule": 0, "block": 256, "tile": t, "grid_per_cu": g, "order": o}
-       for o in (1, 0) for t in (1024, 4096) for g in (2, 4)]
+    + [{"schedule": 0, "block": 256, "tile": 256, "grid_per_cu": g, "order": o}
+       for o in (1, 0) for g in (4, 8)]
     + [{"schedule": 2, "block": b, "tile": 256, "grid_per_cu": 1, "order": o}
        for o in (1, 2) for b in (128, 256)]
     + [{"schedule": 2, "block": 256, "tile": 256, "grid_per_cu": 1, "order": 1, "split_nmax": k}

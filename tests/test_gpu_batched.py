@@ -108,8 +108,9 @@ def test_full_batched_workload_equals_solo():
 
 
 @pytest.mark.parametrize("tuning", [
-    {"schedule": 0, "tile": 2048, "block": 256, "grid_per_cu": 4, "order": 0},
+    {"schedule": 0, "tile": 256, "block": 256, "grid_per_cu": 4, "order": 0},
     {"schedule": 0, "tile": 256, "block": 64, "grid_per_cu": 16, "order": 1},
+    {"schedule": 0, "tile": 256, "block": 128, "grid_per_cu": 1, "order": 2},
     {"schedule": 1, "tile": 256, "block": 256, "grid_per_cu": 1, "order": 2},
     {"schedule": 1, "tile": 512, "block": 128, "grid_per_cu": 1, "order": 0},
     {"schedule": 1, "tile": 256, "block": 64, "grid_per_cu": 1, "order": 1},
@@ -142,8 +143,8 @@ def test_autotune_picks_a_candidate(tmp_path, monkeypatch):
     import paper_2504_07637_amd as boys
     from paper_2504_07637_amd import tuning
     xs, hs, nm, pr = _batch(torch, 200, 60)
-    cands = [{"schedule": 0, "tile": 1024, "block": 256, "grid_per_cu": 2, "order": 0},
-             {"schedule": 0, "tile": 2048, "block": 256, "grid_per_cu": 4, "order": 1},
+    cands = [{"schedule": 0, "tile": 256, "block": 256, "grid_per_cu": 2, "order": 0},
+             {"schedule": 0, "tile": 256, "block": 256, "grid_per_cu": 4, "order": 1},
              {"schedule": 1, "tile": 512, "block": 128, "grid_per_cu": 1, "order": 2}]
     best, times = boys.autotune(xs, nm, pr, cands, warmup=1, reps=2)
     assert best in cands and all(t > 0 for t in times)
