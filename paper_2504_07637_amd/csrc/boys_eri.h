@@ -57,8 +57,11 @@ using boys::PairList;
 
 __shared__ double2 s_eri_exp_tab[256];
 
+// at most 128 VGPRs, 4 waves per SIMD: left alone the compiler takes 129-133 (3 waves);
+// the bound costs 4 spilled VGPRs (20 bytes per lane) and measured 1% faster (3.837
+// against 3.88 ms on the benchmark's 2048 x 2048 pairs; 5 waves spill 38 and lose 23%)
 template <int N>
-__global__ __launch_bounds__(256) void k_eri_ssss(PairList bra, PairList ket, double K,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_eri_ssss(PairList bra, PairList ket, double K,
                                                   double *__restrict__ out, int64_t ld)
 {
     // the exp table in LDS (2-3% faster than through L1 here, measured); every thread

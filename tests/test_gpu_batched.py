@@ -176,3 +176,33 @@ def test_empty_arrays_and_empty_batches():
     from paper_2504_07637_amd import _lib
     assert _lib.lib().boys_eval_batched(None, 0, None) == _lib.OK
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("counts", [[1], [3, 1], [300, 5, 256, 257, 1, 70000]])
+def test_persistent_schedule_small_batches(counts):
+    # the persistent waves with fewer tiles than work queues (8), a single argument, and
+    # arrays whose lengths straddle the 256-argument tile; every class
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    names = ["fp64", "fp32", "fp64plus", "fp32x", "fp32s"]
+    x = inputs.integral_args(sum(counts), seed=77)
+    xd = torch.from_numpy(x).to("cuda")
+    xs, off = [], 0
+    for c in counts:
+        xs.append(xd[off:off + c])
+        off += c
+    nm = [(7 * k + 3) % 17 for k in range(len(counts))]
+    pr = [names[k % 5] for k in range(len(counts))]
+    _say(f"[persistent] lengths {counts}")
+    for gpc in (1, 8):
+        plan = boys.Plan(xs, nm, pr, tuning={"schedule": 0, "tile": 256, "block": 256,
+                                             "grid_per_cu": gpc, "order": 1})
+        for rep in range(2):
+            for o in plan.outs:
+                o.fill_(-3.0)
+            plan.execute()
+            solo = _solo(boys, xs, nm, pr)
+            torch.cuda.synchronize()
+            for k, (o, s) in enumerate(zip(plan.outs, solo)):
+                assert same_bits(o.cpu().numpy(), s.cpu().numpy()).all(), (gpc, rep, k)
+        plan.close()
