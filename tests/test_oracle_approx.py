@@ -267,3 +267,37 @@ def test_mixed_class_beats_all_binary32_in_the_recursion(n):
         gains.append(orc.bits(orc.rel_err(A[m][ok], hi[ok], lo[ok]))
                      - orc.bits(orc.rel_err(S[m][ok], hi[ok], lo[ok])))
     assert max(gains) >= 0.5, (n, gains)
+
+
+def _horner(c, x):
+    p = np.zeros_like(x) + c[-1]
+    for a in c[-2::-1]:
+        p = p * x + a
+    return p
+
+
+@pytest.mark.parametrize("n,gain", [(16, 0.5), (20, 2.0), (36, 5.0)])
+def test_factored_form_beats_the_expanded_rational_in_binary64(n, gain):
+    # The paper's remark in section "Computations": in finite precision the expanded
+    # rational of Eq. qr loses accuracy at higher n that the root-factored form of
+    # Eqs. pqz, pz, qz keeps.  Here the expanded numerator and denominator (the record's
+    # coefficients rounded once to binary64) go through Horner's rule, then Eq. fq in
+    # binary64; the oracle's factored evaluation must be the more accurate F_n.
+    r = orc.record("fp64", n)
+    x = np.arange(GRID) * (r["z"] / GRID)
+    A = [float(a) for a in r["A"]]
+    B = [float(b) for b in r["B"]]
+    Q = _horner(A, x) / _horner(B, x)
+    e = orc.exp_neg(x)
+    Qn = np.ones_like(x)
+    for _ in range(n):
+        Qn = Qn * Q
+    G = x + Qn * np.sqrt(Q) * e
+    Gn = np.ones_like(x)
+    for _ in range(n):
+        Gn = Gn * G
+    F = r["c"] / (Gn * np.sqrt(G))
+    hi, lo = orc.exact_one(x, n)
+    expanded = orc.bits(orc.rel_err(F, hi, lo))
+    factored = ebar("fp64", n)["ebn"]
+    assert factored >= expanded + gain, (n, factored, expanded)
