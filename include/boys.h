@@ -222,10 +222,10 @@ boys_status boys_eval_batched_noalloc(const boys_array *arrays, int32_t count, v
 
 /*
  * Plans: a schedule (tiles in the tuning's order, descriptor and tile tables in
- * device memory, a work counter) and a HIP graph of the batched launch (schedule 0:
- * [reset counter, persistent kernel]; schedule 1: [one workgroup per tile]; schedule 2:
- * [one wave per tile], after [one workgroup per tile] for the store-bound arrays of a
- * split plan) built once for a batch and replayed by boys_plan_execute.  tuning may be
+ * device memory, the work counters of schedule 0) and a HIP graph of the batched launch
+ * (schedule 0: [reset counters, persistent kernel]; schedule 1: [one workgroup per
+ * tile]; schedule 2: [one wave per tile], after [one workgroup per tile] for the
+ * store-bound arrays of a split plan) built once for a batch and replayed by boys_plan_execute.  tuning may be
  * NULL for the defaults: schedule 2, tile 256, block 256, order 1, split_nmax 0.
  * boys_eval_batched uses the defaults.  boys_plan_update replaces the x/out pointers of a
  * batch with the same count, lengths, n_max and precisions (other changes return

@@ -261,7 +261,8 @@ def _arrays(xs, n_maxs, precisions, outs):
 
 
 def boys_eval_batched(xs, n_maxs, precisions, outs=None, stream=None):
-    """Evaluate several arrays in one persistent launch; returns the list of outputs."""
+    """Evaluate several arrays in one batched launch (the default schedule: one wave per
+    256-argument tile); returns the list of outputs."""
     torch = _torch()
     arr, outs = _arrays(xs, n_maxs, precisions, outs)
     dev = xs[0].device if xs else torch.device("cuda")
