@@ -467,8 +467,9 @@ __host__ __device__ __forceinline__ void eval_split(double x, int nbar,
     const boys_tab::RtSet &B = boys_tab::kRt64[nbar];
     const bool below_n = !(x > S::z);  // z_nbar < z_N: below_b implies below_n
     const bool below_b = !(x > B.z);
+    double e = 0.0, num = 1.0, den = x;
     if (below_n) {
-        const double e = exp_rn(__builtin_fmax(-x, -120.0), tab);
+        e = exp_rn(__builtin_fmax(-x, -120.0), tab);
         const double u = factors<double, S::ug_n, S::uq_n, S::ul_n>(x, S::ug, S::uq, S::ul);
         const double v = factors<double, S::vg_n, S::vq_n, S::vl_n>(x, S::vg, S::vq, S::vl);
         const double Q = S::q0 + S::q1 * x + S::q2 * (u / v) * x * x;
@@ -480,21 +481,28 @@ __host__ __device__ __forceinline__ void eval_split(double x, int nbar,
         if (below_b) {
             const double *cu = boys_tab::kRtCoef64 + B.off;
             const double *cv = cu + B.ug_n + 2 * B.uq_n + B.ul_n;
-            const double ub = factors_rt(x, cu, B.ug_n, B.uq_n, B.ul_n);
-            const double vb = factors_rt(x, cv, B.vg_n, B.vq_n, B.vl_n);
-            const double Qb = B.q0 + B.q1 * x + B.q2 * (ub / vb) * x * x;
-            const double Wb = powi_rt(Qb, nbar) * __builtin_sqrt(Qb) * e;
-            const double Gb = x + Wb;
-            double g = B.c / (powi_rt(Gb, nbar) * __builtin_sqrt(Gb));
-            recurse_low<N - 1>(nbar, 2.0 * x, e, g, F);
+            num = factors_rt(x, cu, B.ug_n, B.uq_n, B.ul_n);
+            den = factors_rt(x, cv, B.vg_n, B.vq_n, B.vl_n);
         }
     }
-    if (!below_b) {
+    // the order-nbar approximant below z_nbar and Eq. limf1 past it share one division and
+    // one square root, as in eval_f64_set: ub/vb or 1/x, then F_nbar or F_0
+    const double d = num / den;
+    double C = boys_tab::kC0, G = x, Gn = 1.0;
+    if (below_b) {
+        const double Qb = B.q0 + B.q1 * x + B.q2 * d * x * x;
+        const double Wb = powi_rt(Qb, nbar) * __builtin_sqrt(Qb) * e;
+        G = x + Wb;
+        Gn = powi_rt(G, nbar);
+        C = B.c;
+    }
+    double g = C / (Gn * __builtin_sqrt(G));
+    if (below_b) {
+        recurse_low<N - 1>(nbar, 2.0 * x, e, g, F);
+    } else {
         // Eq. limf1 for rows 0..nbar (z_nbar < x <= z_N) or for every row (x > z_N)
-        const double ix = 1.0 / x;
-        const double f = boys_tab::kC0 / __builtin_sqrt(x);
-        F[0] = f;
-        chain_up<N>(below_n ? nbar : N, ix, f, F);
+        F[0] = g;
+        chain_up<N>(below_n ? nbar : N, d, g, F);
     }
 }
 
