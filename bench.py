@@ -87,11 +87,15 @@ def parse():
                     help="target length of the CPU-baseline sample")
     ap.add_argument("--skip-extras", action="store_true",
                     help="only the headline (for profiling runs)")
-    ap.add_argument("--workload", choices=("boys", "eri", "valu-table"), default="boys",
+    ap.add_argument("--workload", choices=("boys", "eri", "valu-table", "batched"),
+                    default="boys",
                     help="boys: the headline bulk evaluation (default); eri: the consumer "
                          "kernel on its own (contracted (ss|ss)^(m) integrals); valu-table: "
                          "one plain launch per (class, n_max), binary64 and mixed, n_max "
-                         "0..16, on 2^22 integral arguments (for per-order VALU counters)")
+                         "0..16, on 2^22 integral arguments (for per-order VALU counters); "
+                         "batched: the 8,192-array batch with two fixed plans, one workgroup "
+                         "per 1024-argument tile and the persistent schedule (for traces "
+                         "and counters of the batched kernels)")
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="first run one elementwise kernel over 1 GiB (1 GiB read, 1 GiB "
                          "written), a dispatch of known traffic for scaling rocprofv3 "
@@ -379,6 +383,39 @@ def batched(torch, boys, inputs, steps):
     return res
 
 
+BATCH_FIXED = {"workgroup_tile": {"schedule": 1, "block": 256, "tile": 1024, "grid_per_cu": 1,
+                                   "order": 1},
+               "persistent": {"schedule": 0, "block": 256, "tile": 256, "grid_per_cu": 4,
+                              "order": 1}}
+
+
+def batched_fixed(torch, boys, inputs, steps, warmup):
+    """The 8,192-array batch with fixed plans (no tuner), each timed on its own, for
+    profiling runs: algorithmic bytes per replay beside the HIP-event time."""
+    plan_spec = inputs.batch_plan(8192, seed=4)
+    total = sum(l for l, _, _ in plan_spec)
+    xall = torch.from_numpy(inputs.integral_args(total, seed=4)).to("cuda")
+    xs, off = [], 0
+    for l, _, _ in plan_spec:
+        xs.append(xall[off:off + l])
+        off += l
+    nm = [m for _, m, _ in plan_spec]
+    pr = ["fp64" if p == 0 else "fp32" for _, _, p in plan_spec]
+    bytes_ = sum(l * (8 + (m + 1) * (8 if p == 0 else 4)) for l, m, p in plan_spec)
+    res = {"workload": "8,192 arrays, lengths logU[32,65536], n_max U{0..16}, "
+                       "binary64/binary32 alternating", "arguments": total,
+           "alg_bytes_per_replay": bytes_}
+    outs = None
+    for name, t in BATCH_FIXED.items():
+        plan = boys.Plan(xs, nm, pr, tuning=t, outs=outs)
+        outs = plan.outs
+        _, g = timed(torch, plan.execute, steps, warmup)
+        res[name] = {"tuning": t, "plan": describe_plan(t), "ms": g / steps * 1e3,
+                     "hbm_GBs": bytes_ / (g / steps) / 1e9}
+        plan.close()
+    return res
+
+
 ERI_PAIRS = 2048   # contracted shell pairs on each side (9 primitive pairs each)
 ERI_FLOPS_FILE = os.path.join(REPO, "profiles", "flops_eri_ssss_n16.json")
 
@@ -517,6 +554,10 @@ def main():
                 "dtype": "f64", "data": "synthetic", "config": {"workload": r["workload"]}}
         line.update({k: v for k, v in r.items() if k not in line and k != "workload"})
         print(json.dumps(line), flush=True)
+        return
+    if args.workload == "batched":
+        print(json.dumps(batched_fixed(torch, boys, inputs, args.steps, args.warmup)),
+              flush=True)
         return
     if args.workload == "valu-table":
         # one plain launch per (class, n_max): the per-order VALU counters of the batch's
