@@ -49,6 +49,8 @@
 #pragma clang fp contract(off)
 
 namespace boys {
+// internal linkage, like the coefficient tables these functions read
+namespace {
 
 // ---------------------------------------------------------------------------------
 // double-double helpers (error-free transformations)
@@ -577,4 +579,5 @@ __host__ __device__ __forceinline__ void eval_f32s(double x, const double2 *__re
     }
 }
 
+}  // namespace
 }  // namespace boys

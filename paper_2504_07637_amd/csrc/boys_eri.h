@@ -6,6 +6,7 @@
 #include "boys_kernels.h"
 
 namespace boys {
+namespace {
 
 struct PairList {
     const double *p, *px, *py, *pz, *w;  // primitive pairs: p, product centre P, weight
@@ -45,6 +46,7 @@ __host__ __device__ __forceinline__ void eri_ssss_one(const PairList &bra, const
     }
 }
 
+}  // namespace
 }  // namespace boys
 
 namespace {

@@ -165,17 +165,28 @@ def main(dataset=DATASET, out=OUT):
     lines = ["// Generated by gen_tables.py from data/boys_coeffs.txt. Do not edit.",
              "#pragma once",
              "namespace boys_tab {",
+             "// The coefficient arrays of the binary64 and fp32x sets have internal linkage: the",
+             "// device compiler then treats them as ordinary constants and an element read at a",
+             "// fixed index becomes an immediate operand.  Static constexpr arrays with external",
+             "// linkage are emitted as externally initialised device constants, read from memory",
+             "// with scalar loads; the binary32 sets stay that way (one load fetches several",
+             "// coefficients into SGPRs, which their kernels run slightly faster with).  Inside a",
+             "// loop over many inlined sets (the persistent batched kernel) those loads are hoisted",
+             "// and held live, so the binary64 sets, the largest part, are immediates.",
+             "template <int n> struct F32Set;",
+             "namespace {",
              f"constexpr int kMaxN64 = {max64};",
              f"constexpr int kMaxN32 = {max32};",
              f"constexpr int kMaxN32x = {max32x};",
              f"constexpr double kC0 = {lit(c0, False)};  // sqrt(pi)/2",
              "template <int n> struct F64Set;",
-             "template <int n> struct F32Set;",
              "template <int n> struct F32xSet;"]
     for n in range(max64 + 1):
         lines.append(emit_record(recs[("fp64", n)]))
+    lines.append("}  // namespace")
     for n in range(max32 + 1):
         lines.append(emit_record(recs[("fp32", n)]))
+    lines.append("namespace {")
     for n in range(max32x + 1):
         lines.append(emit_record(recs[("fp32x", n)]))
     lines += emit_runtime(recs, "fp64", max64)
@@ -209,6 +220,7 @@ def main(dataset=DATASET, out=OUT):
     for i in range(0, 512, 4):
         lines.append("  " + ", ".join(float.hex(v) for v in tab[i:i + 4]) + ",")
     lines.append("};")
+    lines.append("}  // namespace")
     lines.append("}  // namespace boys_tab")
     text = "\n".join(lines) + "\n"
     tmp = out + ".tmp"
