@@ -87,7 +87,7 @@ def parse():
                     help="target length of the CPU-baseline sample")
     ap.add_argument("--skip-extras", action="store_true",
                     help="only the headline (for profiling runs)")
-    ap.add_argument("--workload", choices=("boys", "eri", "valu-table", "batched"),
+    ap.add_argument("--workload", choices=("boys", "eri", "eri-sides", "valu-table", "batched"),
                     default="boys",
                     help="boys: the headline bulk evaluation (default); eri: the consumer "
                          "kernel on its own (contracted (ss|ss)^(m) integrals); valu-table: "
@@ -95,7 +95,9 @@ def parse():
                          "0..16, on 2^22 integral arguments (for per-order VALU counters); "
                          "batched: the 8,192-array batch with two fixed plans, one workgroup "
                          "per 1024-argument tile and the persistent schedule (for traces "
-                         "and counters of the batched kernels)")
+                         "and counters of the batched kernels); eri-sides: the consumer on "
+                         "the benchmark's lists moved so that every quartet lies below the "
+                         "cut-off, then past it (for per-side VALU counters)")
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="first run one elementwise kernel over 1 GiB (1 GiB read, 1 GiB "
                          "written), a dispatch of known traffic for scaling rocprofv3 "
@@ -420,6 +422,42 @@ ERI_PAIRS = 2048   # contracted shell pairs on each side (9 primitive pairs each
 ERI_FLOPS_FILE = os.path.join(REPO, "profiles", "flops_eri_ssss_n16.json")
 
 
+VALU_WAVE_ISSUE_PER_S = 1024 * 2.4e9 / 4  # 1024 SIMDs, one wave64 instruction per 4 cycles
+
+
+def below_fraction(pairs, z):
+    """The share of the primitive quartets of a pair list with itself whose argument
+    T = rho |P - Q|^2 lies below the cut-off z (not T > z), formed with the kernel's
+    operations in the kernel's order, so the classification is the kernel's."""
+    p, px, py, pz = pairs[0], pairs[1], pairs[2], pairs[3]
+    below = 0
+    for a0 in range(0, p.size, 256):
+        a = slice(a0, a0 + 256)
+        pq = p[a, None] * p[None, :]
+        spq = p[a, None] + p[None, :]
+        rho = pq / spq
+        dx = px[a, None] - px[None, :]
+        dy = py[a, None] - py[None, :]
+        dz = pz[a, None] - pz[None, :]
+        T = rho * (dx * dx + dy * dy + dz * dz)
+        below += int(np.count_nonzero(~(T > z)))
+    return below / float(p.size) ** 2
+
+
+def one_side_lists(inputs, side):
+    """The benchmark's pair list with every product centre moved so that every primitive
+    quartet lies on one side of the cut-off at n_max = 16 (z = 74.5): the bra pairs at the
+    origin, the ket pairs 0.03 bohr away for 'below' (T = rho 9e-4 spans 5e-5 .. 41) or 1000
+    bohr away for 'past' (T >= 6e4)."""
+    c, e, w = inputs.s_basis()
+    pairs, start = inputs.shell_pairs(c, e, w, max_pairs=ERI_PAIRS)
+    bra = pairs.copy()
+    bra[1:4] = 0.0
+    ket = bra.copy()
+    ket[1] = 0.03 if side == "below" else 1000.0
+    return bra, ket, start
+
+
 def eri(torch, boys, inputs, steps, warmup):
     """The consumer: contracted (ss|ss)^(m), m = 0..16, over ERI_PAIRS^2 contracted pairs."""
     c, e, w = inputs.s_basis()
@@ -440,25 +478,62 @@ def eri(torch, boys, inputs, steps, warmup):
            "boys_evaluations_per_s": prim / launch_s,
            "values_consumed_per_s": prim * (N_MAX + 1) / launch_s,
            "bytes_stored_per_launch": 8 * (N_MAX + 1) * nc * nc}
-    fl = flops_for(kernel_hash("eri"))
-    if fl is not None:
+    fb = below_fraction(pairs, boys.cutoff(N_MAX, "fp64"))
+    res["below_cutoff_fraction"] = fb
+    prof = eri_profile(kernel_hash("eri"))
+    if prof is not None:
+        fl = prof["flops_per_launch"]
         res["roofline"] = {"bound": "alu", "achieved": fl / launch_s / 1e12,
                            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                            "frac": fl / launch_s / 1e12 / PEAK_FP64_TFLOPS,
                            "flops_per_launch": fl, "kernel": f"k_eri_ssss<{N_MAX}>",
                            "source": "executed binary64 VALU operations by counters"}
+        sides = prof.get("lane_instructions_per_quartet_by_side")
+        if sides is not None:
+            # the instructions the quartets need on their own sides of the cut-off (each
+            # side's count measured on a list with every quartet on that side), against the
+            # VALU issue capacity: what a divergence-free execution would issue
+            useful = fb * sides["below"] + (1.0 - fb) * sides["past"]
+            achieved = useful * prim / 64.0 / launch_s
+            res["roofline"]["valu_issue"] = {
+                "useful_lane_instructions_per_quartet": useful,
+                "lane_instructions_per_quartet_by_side": sides,
+                "achieved_wave_instructions_per_s": achieved,
+                "peak_wave_instructions_per_s": VALU_WAVE_ISSUE_PER_S,
+                "frac": achieved / VALU_WAVE_ISSUE_PER_S,
+                "executed_lane_instructions_per_quartet":
+                    prof.get("executed_lane_instructions_per_quartet")}
     return res
 
 
-def flops_for(hash_now):
-    """Executed binary64 FLOPs per consumer launch (counter runs), if the kernels have not
-    changed since they were taken."""
+def eri_sides(torch, boys, inputs):
+    """For counter runs: the consumer at n_max = 16 on the benchmark's lists with every
+    quartet below the cut-off, then with every quartet past it (two launches each)."""
+    out = None
+    for side in ("below", "past"):
+        bra, ket, start = one_side_lists(inputs, side)
+        S = torch.from_numpy(start).to("cuda")
+        B = torch.from_numpy(bra).to("cuda")
+        K = torch.from_numpy(ket).to("cuda")
+        nc = start.size - 1
+        if out is None:
+            out = boys.empty_out(nc * nc, N_MAX, "fp64")
+        for _ in range(2):
+            boys.boys_eri_ssss(B, S, K, S, N_MAX, out=out)
+        torch.cuda.synchronize()
+    return {"eri_sides": "below then past, two launches each",
+            "quartets_per_launch": float(bra.shape[1]) ** 2}
+
+
+def eri_profile(hash_now):
+    """The consumer's counter figures (executed binary64 FLOPs per launch, VALU lane
+    instructions per quartet), if the kernels have not changed since they were taken."""
     try:
         with open(ERI_FLOPS_FILE) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    return d.get("flops_per_launch") if d.get("kernel_hash") == hash_now else None
+    return d if d.get("kernel_hash") == hash_now and "flops_per_launch" in d else None
 
 
 def serving(torch, duration=10.0):
@@ -554,6 +629,9 @@ def main():
                 "dtype": "f64", "data": "synthetic", "config": {"workload": r["workload"]}}
         line.update({k: v for k, v in r.items() if k not in line and k != "workload"})
         print(json.dumps(line), flush=True)
+        return
+    if args.workload == "eri-sides":
+        print(json.dumps(eri_sides(torch, boys, inputs)), flush=True)
         return
     if args.workload == "batched":
         print(json.dumps(batched_fixed(torch, boys, inputs, args.steps, args.warmup)),

@@ -317,14 +317,21 @@ __host__ __device__ __forceinline__ T factors(T x, const T (&g)[NG > 0 ? NG : 1]
 // that side selects (a product with 1 is exact), so the values are those of two separate
 // branches bit for bit; a wave with lanes on both sides (on the integral workload nearly
 // every wave) issues the division and the square root once instead of once per side.
-template <class S, int N, bool RcpRecursion = false>
+//
+// Side: a caller whose lanes all lie on one side of the cut-off (it has tested
+// !(x > z) itself, the same test) names that side, and the other side's code is not
+// generated; the operations of the side taken are the same.
+enum : int { kBothSides = 0, kBelowCut = 1, kPastCut = 2 };
+
+template <class S, int N, bool RcpRecursion = false, int Side = kBothSides>
 __host__ __device__ __forceinline__ void eval_f64_set(double x, const double2 *__restrict__ tab,
                                                       double (&F)[N + 1])
 {
     // outside the domain (x < 0) the argument becomes NaN, which every step below carries
     // into every row (fmax keeps the exponential's argument finite)
     x = x >= 0.0 ? x : __builtin_nan("");
-    const bool below = !(x > S::z);  // below the cut-off, and NaN
+    // below the cut-off, and NaN
+    const bool below = Side == kBelowCut || (Side == kBothSides && !(x > S::z));
     double e = 0.0, num = 1.0, den = x;
     if (below) {
         e = exp_rn(__builtin_fmax(-x, -120.0), tab);
@@ -361,11 +368,11 @@ __host__ __device__ __forceinline__ void eval_f64_set(double x, const double2 *_
 }
 
 // the binary64 class: Table 1's binary64 approximants, cut-off z_{n,53}
-template <int N>
+template <int N, int Side = kBothSides>
 __host__ __device__ __forceinline__ void eval_f64(double x, const double2 *__restrict__ tab,
                                                   double (&F)[N + 1])
 {
-    eval_f64_set<boys_tab::F64Set<N>, N>(x, tab, F);
+    eval_f64_set<boys_tab::F64Set<N>, N, false, Side>(x, tab, F);
 }
 
 // the binary32-output class computed in binary64: approximants of about 28 bits with the

@@ -10,13 +10,12 @@ template <int N>
 hipError_t launch_eri(const PairList &bra, const PairList &ket, double K, double *out, int64_t ld,
                       hipStream_t s)
 {
-    constexpr int kBlock = 256;
     const int64_t total = (int64_t)bra.count * ket.count;
-    const int64_t grid = (total + kBlock - 1) / kBlock;
+    const int64_t grid = (total + kEriBlock - 1) / kEriBlock;
     if (grid > INT32_MAX)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_eri_ssss<N>), dim3((unsigned)grid), dim3(kBlock), 0, s, bra, ket, K,
-                       out, ld);
+    hipLaunchKernelGGL((k_eri_ssss<N>), dim3((unsigned)grid), dim3(kEriBlock), 0, s, bra, ket,
+                       K, out, ld);
     return hipGetLastError();
 }
 

@@ -75,3 +75,53 @@ def test_full_size_workload_sampled():
         g = got[:, i * nc:(i + 1) * nc].cpu().numpy()
         msg = report_mismatch(f"eri row {i}", g, want)
         assert not msg, msg
+
+
+def _ragged_list(rng, count, max_prim, centre):
+    """count contracted pairs of 1..max_prim primitive pairs each; centre(k) gives the
+    product centre of primitive pair k."""
+    sizes = rng.integers(1, max_prim + 1, count)
+    start = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    n = int(start[-1])
+    P = np.array([centre(k) for k in range(n)], dtype=np.float64).reshape(n, 3)
+    pairs = np.stack([rng.uniform(0.3, 6.0, n), P[:, 0], P[:, 1], P[:, 2],
+                      rng.uniform(0.1, 1.0, n)])
+    return pairs, start
+
+
+@pytest.mark.parametrize("n", [0, 7, 16, 36])
+def test_every_argument_below_the_cut_off(n):
+    # coincident centres: every T is 0, so every lane of every wave-step lies below the
+    # cut-off and queues its argument; a window then holds one step and the next step is
+    # carried into the following window
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    rng = np.random.default_rng(31 + n)
+    bra, bs = _ragged_list(rng, 37, 5, lambda k: (0.25, -1.0, 2.0))
+    ket, ks = _ragged_list(rng, 53, 4, lambda k: (0.25, -1.0, 2.0))
+    _say(f"[eri] all below the cut-off, n_max={n}, {bs.size - 1} x {ks.size - 1}")
+    got = boys.boys_eri_ssss(*_dev(torch, bra, bs), *_dev(torch, ket, ks), n)
+    torch.cuda.synchronize()
+    msg = report_mismatch(f"eri all-below n_max={n}", got.cpu().numpy(),
+                          orc.eri_ssss(bra, bs, ket, ks, n))
+    assert not msg, msg
+
+
+@pytest.mark.parametrize("n", [3, 16, 30])
+def test_lanes_on_both_sides_in_blocks(n):
+    # kets alternate in runs between coincident centres (every argument below the cut-off)
+    # and distant ones (every argument past it), with ragged primitive counts, so that
+    # windows fill, carry and mix lanes of both sides and of different lengths
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    rng = np.random.default_rng(77 + n)
+    bra, bs = _ragged_list(rng, 29, 6, lambda k: (0.0, 0.0, 0.0))
+    far = rng.uniform(40.0, 80.0, 4000)  # T >= 0.15 * 40^2, past every cut-off
+    ket, ks = _ragged_list(rng, 150, 7,
+                           lambda k: (0.0, 0.0, 0.0) if (k // 23) % 2 else (far[k], 0.0, 0.0))
+    _say(f"[eri] mixed sides, n_max={n}, {bs.size - 1} x {ks.size - 1}")
+    got = boys.boys_eri_ssss(*_dev(torch, bra, bs), *_dev(torch, ket, ks), n)
+    torch.cuda.synchronize()
+    want = orc.eri_ssss(bra, bs, ket, ks, n)
+    msg = report_mismatch(f"eri mixed sides n_max={n}", got.cpu().numpy(), want)
+    assert not msg, msg
