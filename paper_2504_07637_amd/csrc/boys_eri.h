@@ -36,6 +36,7 @@ namespace {
 // evaluate the long-range branch in lockstep.  Each sum still adds the same terms in the
 // same order, and each F_m comes from the same operations (eval_f64 with its side named),
 // so the results are those of the plain per-lane loop bit for bit.
+// windows of 4 steps: 2 measured 14% slower at n_max = 16, 6 or 8 no faster (more registers)
 constexpr int kEriWindow = 4;
 constexpr int kEriBlock = 256;  // threads per workgroup: 4 waves, each with its LDS rows
 
