@@ -142,3 +142,37 @@ def test_kernel_hash_ignores_comments(tmp_path, monkeypatch):
     assert bench.kernel_hash() == h1 and bench.kernel_hash("eri") != he
     src.write_text("int a;\nint c;\n")
     assert bench.kernel_hash() != h1
+
+
+def test_consumer_side_helpers_of_the_benchmark():
+    # the share of quartets below the cut-off, against a plain loop over the quartets with
+    # the kernel's operation order; and the one-side lists really put every quartet on
+    # their side of the n_max = 16 cut-off
+    import numpy as np
+    import bench
+    from paper_2504_07637_amd import inputs
+    g = np.random.default_rng(3)
+    n = 300
+    pairs = np.stack([g.uniform(0.1, 50.0, n), g.normal(0, 2, n), g.normal(0, 2, n),
+                      g.normal(0, 2, n), g.uniform(0.1, 1.0, n)])
+    z = 20.0
+    below = 0
+    for a in range(n):
+        for b in range(n):
+            p, q = pairs[0, a], pairs[0, b]
+            pq = p * q
+            rho = pq / (p + q)
+            dx, dy, dz = (pairs[1, a] - pairs[1, b], pairs[2, a] - pairs[2, b],
+                          pairs[3, a] - pairs[3, b])
+            T = rho * (dx * dx + dy * dy + dz * dz)
+            below += not (T > z)
+    assert bench.below_fraction(pairs, z) == below / n ** 2
+    z16 = 74.50682535593259
+    for side in ("below", "past"):
+        bra, ket, start = bench.one_side_lists(inputs, side)
+        p, q = bra[0][::37], ket[0][::41]
+        rho = p[:, None] * q[None, :] / (p[:, None] + q[None, :])
+        d2 = (bra[1][::37, None] - ket[1][None, ::41]) ** 2
+        T = rho * d2
+        assert (T <= z16).all() if side == "below" else (T > z16).all()
+        assert start[-1] == bra.shape[1] == ket.shape[1]
