@@ -125,3 +125,25 @@ def test_lanes_on_both_sides_in_blocks(n):
     want = orc.eri_ssss(bra, bs, ket, ks, n)
     msg = report_mismatch(f"eri mixed sides n_max={n}", got.cpu().numpy(), want)
     assert not msg, msg
+
+
+@pytest.mark.parametrize("n", [5, 16])
+def test_special_pair_values(n):
+    # zero and negative exponents (T = 0, T < 0: NaN), infinite and NaN centres and weights,
+    # mixed into ordinary pairs: every output equals the oracle's, NaN for NaN
+    torch = require_gpu()
+    import paper_2504_07637_amd as boys
+    rng = np.random.default_rng(5 + n)
+    bra, bs = _ragged_list(rng, 21, 4, lambda k: (0.1 * k, 0.0, 0.3))
+    ket, ks = _ragged_list(rng, 67, 3, lambda k: (0.0, 0.05 * k, -0.2))
+    bra[0, 3], bra[0, 7] = 0.0, -1.5
+    bra[1, 11], bra[4, 13] = np.inf, np.nan
+    ket[0, 5], ket[2, 9], ket[3, 17] = -0.25, -np.inf, np.nan
+    ket[4, 21] = np.inf
+    _say(f"[eri] special values, n_max={n}")
+    got = boys.boys_eri_ssss(*_dev(torch, bra, bs), *_dev(torch, ket, ks), n)
+    torch.cuda.synchronize()
+    want = orc.eri_ssss(bra, bs, ket, ks, n)
+    assert np.isnan(want).any() and np.isfinite(want).any()
+    msg = report_mismatch(f"eri special n_max={n}", got.cpu().numpy(), want)
+    assert not msg, msg
