@@ -258,14 +258,18 @@ __host__ __device__ __forceinline__ float div_odd(float t)
     }
 }
 
+// The evaluations below hand each F_m to put(m, F_m) as they form it; the forms that fill
+// an array F are the same code with put storing into F.  A consumer that adds the values
+// into sums as they come then holds no array of N+1 values.
+
 // downward recursion of Eq. r from F[M] to F[0], unrolled at compile time
-template <int M, typename T>
-__host__ __device__ __forceinline__ void recurse_down(T x2, T e, T f, T *F)
+template <int M, typename T, class Put>
+__host__ __device__ __forceinline__ void recurse_down_each(T x2, T e, T f, Put &put)
 {
     if constexpr (M >= 1) {
         const T g = div_odd<M>(x2 * f + e);
-        F[M - 1] = g;
-        recurse_down<M - 1, T>(x2, e, g, F);
+        put(M - 1, g);
+        recurse_down_each<M - 1, T>(x2, e, g, put);
     }
 }
 
@@ -273,8 +277,8 @@ __host__ __device__ __forceinline__ void recurse_down(T x2, T e, T f, T *F)
 // correctly rounded division: one operation instead of three, for the classes with
 // binary32 outputs, whose values need far less than the working precision (the downward
 // recursion damps the extra rounding)
-template <int M, typename T>
-__host__ __device__ __forceinline__ void recurse_down_rcp(T x2, T e, T f, T *F)
+template <int M, typename T, class Put>
+__host__ __device__ __forceinline__ void recurse_down_rcp_each(T x2, T e, T f, Put &put)
 {
     if constexpr (M >= 1) {
         T g = x2 * f + e;
@@ -284,9 +288,16 @@ __host__ __device__ __forceinline__ void recurse_down_rcp(T x2, T e, T f, T *F)
             else
                 g = g * kOddRcp.f[M];
         }
-        F[M - 1] = g;
-        recurse_down_rcp<M - 1, T>(x2, e, g, F);
+        put(M - 1, g);
+        recurse_down_rcp_each<M - 1, T>(x2, e, g, put);
     }
+}
+
+template <int M, typename T>
+__host__ __device__ __forceinline__ void recurse_down_rcp(T x2, T e, T f, T *F)
+{
+    auto put = [F](int m, T v) { F[m] = v; };
+    recurse_down_rcp_each<M, T>(x2, e, f, put);
 }
 
 // one of u, v: gathered monic polynomial (Horner), then quadratic, then linear factors
@@ -323,9 +334,10 @@ __host__ __device__ __forceinline__ T factors(T x, const T (&g)[NG > 0 ? NG : 1]
 // generated; the operations of the side taken are the same.
 enum : int { kBothSides = 0, kBelowCut = 1, kPastCut = 2 };
 
-template <class S, int N, bool RcpRecursion = false, int Side = kBothSides>
-__host__ __device__ __forceinline__ void eval_f64_set(double x, const double2 *__restrict__ tab,
-                                                      double (&F)[N + 1])
+template <class S, int N, bool RcpRecursion = false, int Side = kBothSides, class Put>
+__host__ __device__ __forceinline__ void eval_f64_set_each(double x,
+                                                           const double2 *__restrict__ tab,
+                                                           Put &put)
 {
     // outside the domain (x < 0) the argument becomes NaN, which every step below carries
     // into every row (fmax keeps the exponential's argument finite)
@@ -350,21 +362,29 @@ __host__ __device__ __forceinline__ void eval_f64_set(double x, const double2 *_
     // F_n below the cut-off; past it F_0 of Eq. limf1 (x = +inf gives 0 everywhere)
     const double f = C / (Gn * __builtin_sqrt(G));
     if (below) {
-        F[N] = f;
+        put(N, f);
         if constexpr (RcpRecursion)
-            recurse_down_rcp<N, double>(2.0 * x, e, f, F);
+            recurse_down_rcp_each<N, double>(2.0 * x, e, f, put);
         else
-            recurse_down<N, double>(2.0 * x, e, f, F);
+            recurse_down_each<N, double>(2.0 * x, e, f, put);
     } else {
         // Eq. limf1 for every m, generated upward with d = 1/x
         double g = f;
-        F[0] = g;
+        put(0, g);
 #pragma unroll
         for (int m = 1; m <= N; ++m) {
             g = g * (m - 0.5) * d;
-            F[m] = g;
+            put(m, g);
         }
     }
+}
+
+template <class S, int N, bool RcpRecursion = false, int Side = kBothSides>
+__host__ __device__ __forceinline__ void eval_f64_set(double x, const double2 *__restrict__ tab,
+                                                      double (&F)[N + 1])
+{
+    auto put = [&F](int m, double v) { F[m] = v; };
+    eval_f64_set_each<S, N, RcpRecursion, Side>(x, tab, put);
 }
 
 // the binary64 class: Table 1's binary64 approximants, cut-off z_{n,53}
@@ -373,6 +393,14 @@ __host__ __device__ __forceinline__ void eval_f64(double x, const double2 *__res
                                                   double (&F)[N + 1])
 {
     eval_f64_set<boys_tab::F64Set<N>, N, false, Side>(x, tab, F);
+}
+
+// the same, each F_m handed to put(m, F_m)
+template <int N, int Side = kBothSides, class Put>
+__host__ __device__ __forceinline__ void eval_f64_each(double x, const double2 *__restrict__ tab,
+                                                       Put &put)
+{
+    eval_f64_set_each<boys_tab::F64Set<N>, N, false, Side>(x, tab, put);
 }
 
 // the binary32-output class computed in binary64: approximants of about 28 bits with the

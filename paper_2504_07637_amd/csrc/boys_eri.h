@@ -40,6 +40,17 @@ namespace {
 constexpr int kEriWindow = 4;
 constexpr int kEriBlock = 256;  // threads per workgroup: 4 waves, each with its LDS rows
 
+// At the orders where it buys a wave per SIMD, the values go straight from the evaluation
+// into the sums and into the LDS rows (eval_f64_each), with no array of N+1 values, and the
+// exp table is read through L1: 20-24 run 3 waves per SIMD instead of 2 (146-162 VGPRs
+// instead of 172-196; 7% faster at 20 and 24), 34-36 run 2 instead of 1 (37% faster at
+// 36).  Elsewhere the occupancy is the same either way and the array form with the table in
+// LDS is ahead (2% at 16, 4% at 28 and 30).
+constexpr bool eri_streams(int n)
+{
+    return (n >= 20 && n <= 24) || n >= 34;
+}
+
 using boys::PairList;
 
 __shared__ double2 s_eri_exp_tab[256];
@@ -60,9 +71,14 @@ __global__ __launch_bounds__(kEriBlock) void k_eri_ssss(PairList bra, PairList k
     // per wave: the window's below-cut-off arguments and their F_0..F_N
     __shared__ double s_arg[kEriBlock / 64][64];
     __shared__ double s_val[kEriBlock / 64][N + 1][64];
-    // the exp table in LDS (2-3% faster than through L1 here, measured); every thread
-    // reaches the barrier in load_exp_table before any leaves
-    load_exp_table(s_eri_exp_tab);
+    constexpr bool stream = eri_streams(N);
+    // otherwise the exp table in LDS (2-3% faster than through L1 there, measured); every
+    // thread reaches the barrier in load_exp_table before any leaves
+    const double2 *tab = reinterpret_cast<const double2 *>(boys_tab::kExp2Tab);
+    if constexpr (!stream) {
+        load_exp_table(s_eri_exp_tab);
+        tab = s_eri_exp_tab;
+    }
     const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63u);
     double *arg = s_arg[wave];
     double(*val)[64] = s_val[wave];
@@ -157,28 +173,45 @@ __global__ __launch_bounds__(kEriBlock) void k_eri_ssss(PairList bra, PairList k
         wave_order();
         // the queue, one argument per lane, all below the cut-off
         if (lane < queued) {
-            double F[N + 1];
-            boys::eval_f64<N, boys::kBelowCut>(arg[lane], s_eri_exp_tab, F);
+            if constexpr (stream) {
+                auto put = [&](int m, double v) { val[m][lane] = v; };
+                boys::eval_f64_each<N, boys::kBelowCut>(arg[lane], tab, put);
+            } else {
+                double F[N + 1];
+                boys::eval_f64<N, boys::kBelowCut>(arg[lane], tab, F);
 #pragma unroll
-            for (int m = 0; m <= N; ++m)
-                val[m][lane] = F[m];
+                for (int m = 0; m <= N; ++m)
+                    val[m][lane] = F[m];
+            }
         }
         wave_order();
         // the window's steps in order
 #pragma unroll
         for (int t = 0; t < kEriWindow; ++t) {
             if (t < steps && has[t]) {
-                double F[N + 1];
-                if (below[t]) {
+                if constexpr (stream) {
+                    const double st = S[t];
+                    if (below[t]) {
+#pragma unroll
+                        for (int m = 0; m <= N; ++m)
+                            acc[m] = __builtin_fma(st, val[m][slot[t]], acc[m]);
+                    } else {
+                        auto add = [&](int m, double v) { acc[m] = __builtin_fma(st, v, acc[m]); };
+                        boys::eval_f64_each<N, boys::kPastCut>(T[t], tab, add);
+                    }
+                } else {
+                    double F[N + 1];
+                    if (below[t]) {
+#pragma unroll
+                        for (int m = 0; m <= N; ++m)
+                            F[m] = val[m][slot[t]];
+                    } else {
+                        boys::eval_f64<N, boys::kPastCut>(T[t], tab, F);
+                    }
 #pragma unroll
                     for (int m = 0; m <= N; ++m)
-                        F[m] = val[m][slot[t]];
-                } else {
-                    boys::eval_f64<N, boys::kPastCut>(T[t], s_eri_exp_tab, F);
+                        acc[m] = __builtin_fma(S[t], F[m], acc[m]);
                 }
-#pragma unroll
-                for (int m = 0; m <= N; ++m)
-                    acc[m] = __builtin_fma(S[t], F[m], acc[m]);
             }
         }
         wave_order();  // the next window rewrites the queue
