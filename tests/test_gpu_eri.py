@@ -57,23 +57,26 @@ def test_empty_lists_and_primitive_free_pairs():
     assert out.shape == (6, 0)
 
 
-def test_full_size_workload_sampled():
-    # the benchmark's 2048 x 2048 contracted pairs (9 primitive pairs each), n_max = 16:
-    # 24 bra rows in full against the oracle
+@pytest.mark.parametrize("n,nrows", [(16, 22), (22, 6), (36, 6)])
+def test_full_size_workload_sampled(n, nrows):
+    # the benchmark's 2048 x 2048 contracted pairs (9 primitive pairs each): sampled bra
+    # rows in full against the oracle, at n_max = 16 (the benchmark's order) and at two
+    # orders of the streaming form (22, 36)
     torch = require_gpu()
     import paper_2504_07637_amd as boys
     c, e, w = inputs.s_basis()
     pairs, start = inputs.shell_pairs(c, e, w, max_pairs=2048)
     nc = start.size - 1
-    _say(f"[eri] full {nc} x {nc}, n_max=16")
-    got = boys.boys_eri_ssss(*_dev(torch, pairs, start), *_dev(torch, pairs, start), 16)
+    _say(f"[eri] full {nc} x {nc}, n_max={n}")
+    got = boys.boys_eri_ssss(*_dev(torch, pairs, start), *_dev(torch, pairs, start), n)
     torch.cuda.synchronize()
-    rows = np.unique(np.concatenate([[0, nc - 1], np.random.default_rng(9).integers(0, nc, 22)]))
+    rows = np.unique(np.concatenate([[0, nc - 1],
+                                     np.random.default_rng(9 + n).integers(0, nc, nrows)]))
     for i in rows:
         sub = pairs[:, start[i]:start[i + 1]]
-        want = orc.eri_ssss(sub, np.array([0, sub.shape[1]], dtype=np.int32), pairs, start, 16)
+        want = orc.eri_ssss(sub, np.array([0, sub.shape[1]], dtype=np.int32), pairs, start, n)
         g = got[:, i * nc:(i + 1) * nc].cpu().numpy()
-        msg = report_mismatch(f"eri row {i}", g, want)
+        msg = report_mismatch(f"eri row {i} n_max={n}", g, want)
         assert not msg, msg
 
 
